@@ -164,11 +164,11 @@ def from_edges(n: int, edges: Iterable[Tuple[int, int]], weights: Optional[Seque
     return CSR(n, off, tgt, w, name)
 
 
-def cliques(k: int, s: int, bridges: Sequence[Tuple[int, int]] = ()) -> CSR:
+def cliques(k: int, s: int, bridges: Sequence[Tuple[int, int]] = (), name: str = "") -> CSR:
     """k disjoint complete graphs K_s (clique q on ids q*s .. q*s+s-1), optional extra edges."""
     edges = [(q * s + i, q * s + j) for q in range(k) for i in range(s) for j in range(i + 1, s)]
     edges += list(bridges)
-    return from_edges(k * s, edges, name="cliques%dx%d" % (k, s))
+    return from_edges(k * s, edges, name=name or "cliques%dx%d" % (k, s))
 
 
 _RMAT = re.compile(r"^rmat(\d+)-(\d+)$")

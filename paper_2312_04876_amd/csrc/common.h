@@ -1,0 +1,251 @@
+// Shared device-side definitions of the gfx950 Louvain kernels.
+//
+// Arithmetic is exact: community weights, K' and Sigma' are int32 when the
+// total weight W < 2^31 and int64 otherwise; delta-modularity scores
+// W*K_{i->c} - K_i*Sigma_c (Eq. 2 scaled by W^2/2) are int64 in the first
+// case and 128-bit in the second.  Sums of gains are accumulated exactly in
+// 128 bits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/louvain.h"
+
+namespace lv {
+
+typedef __int128 i128;
+
+// ---------------------------------------------------------------------------
+// Type configurations: WT = stored weight of the current level, ST = K',
+// Sigma' and table accumulator, SC = score arithmetic.
+template <typename WT_, typename ST_, typename SC_>
+struct Cfg {
+    typedef WT_ WT;
+    typedef ST_ ST;
+    typedef SC_ SC;
+};
+typedef Cfg<int32_t, int32_t, int64_t> CfgNarrow;  // W < 2^31, every level
+typedef Cfg<int32_t, int64_t, i128> CfgWideIn;     // W >= 2^31, input level (int32 weights)
+typedef Cfg<int64_t, int64_t, i128> CfgWide;       // W >= 2^31, aggregated levels
+
+// ---------------------------------------------------------------------------
+// Degree bins.  A vertex (or, in aggregation, a community with its total
+// member degree) goes to the bin of its row length d:
+//   bin 0: d in [1, 8]      8 lanes per row, 16-slot LDS table
+//   bin 1: d in [9, 32]     32 lanes, 64 slots
+//   bin 2: d in [33, 128]   one wavefront, 256 slots
+//   bin 3: d in [129, 512]  one wavefront, 1024 slots
+//   bin 4: d in [513, 4096] one 256-thread workgroup, up to 8192 LDS slots
+//   bin 5: d > 4096         one 256-thread workgroup, table in HBM
+// Every table has at least twice as many slots as the row has entries, so
+// linear probing always finds a free slot.
+constexpr int NBINS = 6;
+constexpr int BIN_HI[NBINS] = {8, 32, 128, 512, 4096, 0x7fffffff};
+constexpr int LDS_MAX_DEG = 4096;
+constexpr int BLOCK_LOG2S_MAX = 13;  // 8192 slots
+constexpr int HUB_THREADS = 256;
+
+__host__ __device__ inline int bin_of(int64_t d)
+{
+    if (d <= 0) return -1;
+    if (d <= 8) return 0;
+    if (d <= 32) return 1;
+    if (d <= 128) return 2;
+    if (d <= 512) return 3;
+    if (d <= LDS_MAX_DEG) return 4;
+    return 5;
+}
+
+// HBM table size for a hub row of length d (a multiple of 64, >= 2d).
+__host__ __device__ inline int64_t hub_slots(int64_t d) { return ((2 * d + 63) / 64) * 64; }
+
+// ---------------------------------------------------------------------------
+// Scalars shared between kernels and the host (one copy in the workspace).
+struct DevScalars {
+    unsigned long long sumN[LOUVAIN_MAX_ITERATIONS + 1][2];  // 128-bit gain sums per iteration
+    double dq[LOUVAIN_MAX_ITERATIONS + 1];
+    unsigned long long moves[LOUVAIN_MAX_ITERATIONS + 1];
+    unsigned long long processed[LOUVAIN_MAX_ITERATIONS + 1];
+    unsigned long long scanned[LOUVAIN_MAX_ITERATIONS + 1];
+    int32_t done;
+    int32_t iters;
+    int32_t bin_count[8];   // active vertices per bin in the current round
+    int32_t bin_cursor[8];  // fill cursors of the binning step
+    int32_t bin_total[8];   // vertices per bin (binning step)
+    int32_t mv_count;       // deferred moves of the current round (deterministic mode)
+    int32_t pad0;
+    // --- fields above are cleared at the start of every local-moving phase ---
+    int32_t err;            // validation: bit 0 offsets, 1 targets, 2 weights
+    int32_t pad1;
+    unsigned long long scan_total;
+    unsigned long long W;
+    unsigned long long sigma;       // sum of intra-community entries
+    unsigned long long s2[2];       // 128-bit sum of Sigma_c^2
+    unsigned long long work[16][5]; // algorithmic work counters per kernel family
+    int32_t pad[16];
+};
+
+// Work-counter slots (DevScalars::work[k]): move bins 0..5
+// [vertices, entries, new keys, moves, -], aggregation bins 6..11
+// [communities, members, entries, emitted, -].
+constexpr int WORK_MOVE = 0;
+constexpr int WORK_AGG = 6;
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+
+__device__ inline uint32_t hash32(uint32_t k) { return k * 2654435761u; }
+
+// Exact 128-bit accumulation into a two-word (lo, hi) counter: the carry out
+// of the low word of this addition goes into the high word, so the total is
+// exact regardless of order.
+__device__ inline void atomic_add_i128(unsigned long long *acc, i128 x)
+{
+    if (x == 0) return;
+    unsigned long long lo = (unsigned long long)x;
+    unsigned long long hi = (unsigned long long)(x >> 64);
+    unsigned long long old = atomicAdd(&acc[0], lo);
+    unsigned long long carry = (old + lo < old) ? 1ull : 0ull;
+    if (hi + carry) atomicAdd(&acc[1], hi + carry);
+}
+
+__host__ __device__ inline i128 join_i128(unsigned long long lo, unsigned long long hi)
+{
+    return (i128)(((unsigned __int128)hi << 64) | (unsigned __int128)lo);
+}
+
+// Correctly rounded int128 -> double: the top 64 significant bits with every
+// lower bit folded into a sticky bit, converted once, then scaled exactly.
+__host__ __device__ inline double i128_to_f64(i128 v)
+{
+    const bool neg = v < 0;
+    unsigned __int128 u = neg ? (unsigned __int128)(-(v + 1)) + 1u : (unsigned __int128)v;
+    const uint64_t hi = (uint64_t)(u >> 64), lo = (uint64_t)u;
+    double r;
+    if (hi == 0) {
+        r = (double)lo;
+    } else {
+        const int s = __builtin_clzll(hi);
+        uint64_t top = s ? (hi << s) | (lo >> (64 - s)) : hi;
+        const uint64_t rest = s ? (lo << s) : lo;
+        top |= (rest != 0) ? 1u : 0u;
+        r = ldexp((double)top, 64 - s);
+    }
+    return neg ? -r : r;
+}
+
+// Iteration delta-Q as in the tolerance test of Alg. 2: 2*sumN / W^2 in FP64.
+__host__ __device__ inline double iteration_dq(i128 sumN, unsigned long long W)
+{
+    if (W == 0) return 0.0;
+    const double w = (double)(int64_t)W;
+    return 2.0 * i128_to_f64(sumN) / (w * w);
+}
+
+// Round of vertex v in iteration it of pass p: the top round_bits bits of
+// the SplitMix64 output (Steele, Lea and Flood 2014) for counter
+// (p << 40 | it << 32 | v) under key seed.
+__host__ __device__ inline int round_of(uint64_t seed, int round_bits, int pass, int it, int v)
+{
+    if (round_bits <= 0) return 0;
+    const uint64_t ctr = ((uint64_t)(uint32_t)pass << 40) | ((uint64_t)(uint32_t)(it & 0xFF) << 32) |
+                         (uint64_t)(uint32_t)v;
+    uint64_t z = seed + (ctr + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (int)(z >> (64 - round_bits));
+}
+
+// Row of vertex v: [off[v], off[v] + length) with length from the degree
+// array of a holey level or from the next offset of a dense one.
+__device__ inline int row_len(const int32_t *off, const int32_t *deg, int v)
+{
+    return deg ? deg[v] : off[v + 1] - off[v];
+}
+
+template <typename T>
+__device__ inline T shfl_xor_t(T x, int mask);
+
+template <>
+__device__ inline int32_t shfl_xor_t<int32_t>(int32_t x, int mask)
+{
+    return __shfl_xor(x, mask, 64);
+}
+
+template <>
+__device__ inline int64_t shfl_xor_t<int64_t>(int64_t x, int mask)
+{
+    const int lo = __shfl_xor((int)(uint32_t)(uint64_t)x, mask, 64);
+    const int hi = __shfl_xor((int)(uint32_t)((uint64_t)x >> 32), mask, 64);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+template <>
+__device__ inline unsigned long long shfl_xor_t<unsigned long long>(unsigned long long x, int mask)
+{
+    return (unsigned long long)shfl_xor_t<int64_t>((int64_t)x, mask);
+}
+
+template <>
+__device__ inline i128 shfl_xor_t<i128>(i128 x, int mask)
+{
+    const int64_t lo = shfl_xor_t<int64_t>((int64_t)(uint64_t)x, mask);
+    const int64_t hi = shfl_xor_t<int64_t>((int64_t)(x >> 64), mask);
+    return join_i128((unsigned long long)lo, (unsigned long long)hi);
+}
+
+// Order of wavefront-level phases that communicate through LDS: all lanes
+// of the wavefront finish their LDS accesses before any lane goes on.
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ inline void atomic_add_t(T *p, T v);
+
+template <>
+__device__ inline void atomic_add_t<int32_t>(int32_t *p, int32_t v)
+{
+    atomicAdd(p, v);
+}
+
+template <>
+__device__ inline void atomic_add_t<int64_t>(int64_t *p, int64_t v)
+{
+    atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+
+template <typename SC>
+__device__ inline SC score_min();
+
+template <>
+__device__ inline int64_t score_min<int64_t>()
+{
+    return INT64_MIN;
+}
+
+template <>
+__device__ inline i128 score_min<i128>()
+{
+    return (i128)(((unsigned __int128)1) << 127);
+}
+
+// Wavefront sum of an unsigned 64-bit counter (result in every lane).
+__device__ inline unsigned long long wave_sum_u64(unsigned long long x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += shfl_xor_t<unsigned long long>(x, o);
+    return x;
+}
+
+__device__ inline i128 wave_sum_i128(i128 x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += shfl_xor_t<i128>(x, o);
+    return x;
+}
+
+}  // namespace lv

@@ -1,0 +1,615 @@
+// Scans, fills, validation, degree binning, row reductions, compaction and
+// the small per-round / per-iteration bookkeeping kernels.
+#include "kernels.h"
+
+namespace lv {
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;
+
+__device__ inline int64_t shfl_up_i64(int64_t x, int d)
+{
+    const int lo = __shfl_up((int)(uint32_t)(uint64_t)x, d, 64);
+    const int hi = __shfl_up((int)(uint32_t)((uint64_t)x >> 32), d, 64);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// Exclusive scan of one value per thread across a 256-thread block; returns
+// the exclusive prefix and stores the block total in *block_total.
+__device__ inline int64_t block_exclusive_scan(int64_t x, int64_t *block_total)
+{
+    __shared__ int64_t wsum[SCAN_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t incl = x;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t y = shfl_up_i64(incl, d);
+        if (lane >= d) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int64_t wbase = 0, tot = 0;
+    for (int k = 0; k < SCAN_THREADS / 64; ++k) {
+        if (k < wave) wbase += wsum[k];
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *block_total = tot;
+    return wbase + incl - x;
+}
+
+template <typename TI>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const TI *in, int64_t n,
+                                                              int64_t *part)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) s += (int64_t)in[base + k];
+    int64_t tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// One block scans the block totals in place (exclusive) and records the total.
+template <typename TO>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(int64_t *part, int64_t nb,
+                                                                TO *out, int64_t n,
+                                                                unsigned long long *total)
+{
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_THREADS) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t x = i < nb ? part[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan(x, &tot);
+        if (i < nb) part[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        out[n] = (TO)carry;
+        if (total) *total = (unsigned long long)carry;
+    }
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const TI *in, TO *out, int64_t n,
+                                                             const int64_t *part)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    TI v[SCAN_ITEMS];
+    int64_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : (TI)0;
+        s += (int64_t)v[k];
+    }
+    int64_t tot;
+    int64_t run = part[blockIdx.x] + block_exclusive_scan(s, &tot);
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = (TO)run;
+        run += (int64_t)v[k];
+    }
+}
+
+inline int grid_for(int64_t n, int threads, int cap = 8192)
+{
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+__global__ void k_iota(int32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+__global__ void k_init_slab(int32_t *keys, unsigned char *vals, int64_t slots, int vbytes)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < slots;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        keys[i] = -1;
+        if (vbytes == 8)
+            ((int64_t *)vals)[i] = 0;
+        else
+            ((int32_t *)vals)[i] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_validate(int32_t n, int64_t nnz, const int32_t *off,
+                                                  const int32_t *tgt, const int32_t *w,
+                                                  int32_t *err, unsigned long long *W)
+{
+    int e_off = 0, e_tgt = 0, e_w = 0;
+    unsigned long long s = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gid == 0 && (off[0] != 0 || (int64_t)off[n] != nnz)) e_off = 1;
+    for (int64_t i = gid; i < n; i += stride)
+        if (off[i] > off[i + 1]) e_off = 1;
+    for (int64_t e = gid; e < nnz; e += stride) {
+        const int32_t t = tgt[e];
+        const int32_t x = w[e];
+        if (t < 0 || t >= n) e_tgt = 1;
+        if (x < 1) e_w = 1;
+        s += (unsigned long long)(x > 0 ? x : 0);
+    }
+    const int bits = e_off | (e_tgt << 1) | (e_w << 2);
+    if (bits) atomicOr(err, bits);
+    s = wave_sum_u64(s);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(W, s);
+}
+
+__global__ void k_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,
+                                unsigned char *K, unsigned char *Sig, int sbytes)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        Cp[i] = (int32_t)i;
+        size[i] = 1;
+        fa[i] = 1;
+        fb[i] = 0;
+        if (sbytes == 8) {
+            ((int64_t *)K)[i] = 0;
+            ((int64_t *)Sig)[i] = 0;
+        } else {
+            ((int32_t *)K)[i] = 0;
+            ((int32_t *)Sig)[i] = 0;
+        }
+    }
+}
+
+__device__ inline int len_of(const int32_t *off, const int32_t *deg, int v)
+{
+    return deg ? deg[v] : off[v + 1] - off[v];
+}
+
+__global__ __launch_bounds__(256) void k_bin_count(int32_t n, const int32_t *off,
+                                                   const int32_t *deg, int32_t *totals)
+{
+    __shared__ int32_t h[NBINS];
+    if (threadIdx.x < NBINS) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = bin_of(len_of(off, deg, (int)i));
+        if (b >= 0) atomicAdd(&h[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < NBINS && h[threadIdx.x]) atomicAdd(&totals[threadIdx.x], h[threadIdx.x]);
+}
+
+// Append `item` to the list of bin b (wavefront-aggregated atomics); every lane
+// of the wavefront must call this, lanes with b < 0 append nothing.
+__device__ inline void wave_append(int b, int32_t item, const BinInfo &bins, int32_t *cursors,
+                                   int32_t *list)
+{
+    const int lane = threadIdx.x & 63;
+    unsigned long long todo = __ballot(b >= 0);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int bl = __shfl(b, leader, 64);
+        const unsigned long long m = __ballot(b == bl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cursors[bl], __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (b == bl) list[bins.start[bl] + base + __popcll(m & below)] = item;
+        todo &= ~m;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin_fill(int32_t n, const int32_t *off,
+                                                  const int32_t *deg, BinInfo bins,
+                                                  int32_t *cursors, int32_t *binorder)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const int b = i < n ? bin_of(len_of(off, deg, (int)i)) : -1;
+        wave_append(b, (int32_t)i, bins, cursors, binorder);
+    }
+}
+
+__global__ void k_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
+                            const int32_t *deg, int64_t cap, int64_t *out)
+{
+    for (int64_t p = hb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < he;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int64_t d = len_of(off, deg, binorder[p]);
+        if (d > cap) d = cap;
+        out[p - hb] = hub_slots(d);
+    }
+}
+
+// Row reductions with G lanes per row (G <= 64: groups inside a wavefront;
+// G == 256: the whole workgroup).
+template <class C, int G, int OP>
+__global__ __launch_bounds__(256) void k_row_reduce(RowArgs<C> a)
+{
+    typedef typename C::ST ST;
+    __shared__ unsigned long long red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long acc = 0;
+    if constexpr (G <= 64) {
+        constexpr int GPW = 64 / G;
+        const int grp = lane / G, gl = lane % G;
+        const int stride = gridDim.x * 4 * GPW;
+        for (int base = (blockIdx.x * 4 + wave) * GPW; base < a.count; base += stride) {
+            const int idx = base + grp;
+            const bool has = idx < a.count;
+            int v = 0, beg = 0, d = 0;
+            if (has) {
+                v = a.binorder[a.begin + idx];
+                beg = a.off[v];
+                d = len_of(a.off, a.deg, v);
+            }
+            int64_t s = 0;
+            const int lv = (OP == 1 && has) ? a.labels[v] : 0;
+            for (int e = gl; e < d; e += G) {
+                const int64_t x = (int64_t)a.w[beg + e];
+                if (OP == 0 || a.labels[a.tgt[beg + e]] == lv) s += x;
+            }
+            for (int o = G / 2; o > 0; o >>= 1) s += shfl_xor_t<int64_t>(s, o);
+            if (OP == 0) {
+                if (has && gl == 0) {
+                    a.K[v] = (ST)s;
+                    a.Sig[v] = (ST)s;
+                }
+            } else if (gl == 0) {
+                acc += (unsigned long long)s;
+            }
+        }
+    } else {
+        __shared__ int64_t part[4];
+        for (int idx = blockIdx.x; idx < a.count; idx += gridDim.x) {
+            const int v = a.binorder[a.begin + idx];
+            const int beg = a.off[v];
+            const int d = len_of(a.off, a.deg, v);
+            const int lv = OP == 1 ? a.labels[v] : 0;
+            int64_t s = 0;
+            for (int e = threadIdx.x; e < d; e += 256) {
+                const int64_t x = (int64_t)a.w[beg + e];
+                if (OP == 0 || a.labels[a.tgt[beg + e]] == lv) s += x;
+            }
+            for (int o = 32; o > 0; o >>= 1) s += shfl_xor_t<int64_t>(s, o);
+            if (lane == 0) part[wave] = s;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int64_t t = part[0] + part[1] + part[2] + part[3];
+                if (OP == 0) {
+                    a.K[v] = (ST)t;
+                    a.Sig[v] = (ST)t;
+                } else {
+                    acc += (unsigned long long)t;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (OP == 1) {
+        acc = wave_sum_u64(acc);
+        if (lane == 0) red[wave] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long t = red[0] + red[1] + red[2] + red[3];
+            if (t) atomicAdd(a.sigma, t);
+        }
+    }
+}
+
+template <typename ST>
+__global__ __launch_bounds__(256) void k_sum_squares(const ST *Sig, int32_t n,
+                                                     unsigned long long *acc)
+{
+    i128 s = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const i128 x = (i128)Sig[i];
+        s += x * x;
+    }
+    s = wave_sum_i128(s);
+    if ((threadIdx.x & 63) == 0) atomic_add_i128(acc, s);
+}
+
+__global__ __launch_bounds__(256) void k_compact(CompactArgs a)
+{
+    if (*a.done) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.nb; base += stride) {
+        const int32_t p = (int32_t)(base + threadIdx.x);
+        int b = -1;
+        if (p < a.nb) {
+            const int v = a.binorder[p];
+            bool act = a.prune ? (a.flags[v] != 0) : true;
+            if (act && a.round_bits > 0)
+                act = round_of(a.seed, a.round_bits, a.pass, a.it, v) == a.round;
+            if (act) {
+                if (a.prune) a.flags[v] = 0;
+                b = 0;
+                while (b + 1 < NBINS && p >= a.bins.start[b + 1]) ++b;
+            }
+        }
+        wave_append(b, p, a.bins, a.counts, a.worklist);
+    }
+}
+
+template <typename ST>
+__global__ __launch_bounds__(256) void k_apply(const int32_t *mv_v, const int32_t *mv_c,
+                                               const int32_t *mv_count, int32_t *Cp, const ST *K,
+                                               ST *Sig, int32_t *size, int32_t cap,
+                                               const int32_t *done)
+{
+    if (*done) return;
+    int m = *mv_count;
+    if (m > cap) m = cap;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int v = mv_v[k], c = mv_c[k];
+        const int d = Cp[v];
+        const ST kv = K[v];
+        Cp[v] = c;
+        atomic_add_t<ST>(&Sig[d], (ST)-kv);
+        atomic_add_t<ST>(&Sig[c], kv);
+        atomicSub(&size[d], 1);
+        atomicAdd(&size[c], 1);
+    }
+}
+
+__global__ void k_round_end(DevScalars *sc, int it)
+{
+    const int t = threadIdx.x;
+    if (t < NBINS) {
+        const int c = sc->bin_count[t];
+        if (c) atomicAdd(&sc->processed[it], (unsigned long long)c);
+        sc->bin_count[t] = 0;
+    }
+    if (t == 0) sc->mv_count = 0;
+}
+
+__global__ void k_iter_end(DevScalars *sc, int it, double tau)
+{
+    if (threadIdx.x != 0 || sc->done) return;
+    const i128 s = join_i128(sc->sumN[it][0], sc->sumN[it][1]);
+    const double dq = iteration_dq(s, sc->W);
+    sc->dq[it] = dq;
+    sc->iters = it + 1;
+    if (dq <= tau) sc->done = 1;
+}
+
+__global__ void k_mark_used(int32_t n, const int32_t *labels, int32_t *used)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        used[labels[i]] = 1;
+}
+
+__global__ void k_relabel(int32_t n, int32_t *labels, const int32_t *map)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        labels[i] = map[labels[i]];
+}
+
+__global__ void k_comm_count(int32_t n, const int32_t *Cp, const int32_t *off, const int32_t *deg,
+                             int32_t *ccount, int32_t *ctot)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = Cp[i];
+        atomicAdd(&ccount[c], 1);
+        const int d = len_of(off, deg, (int)i);
+        if (d) atomicAdd(&ctot[c], d);
+    }
+}
+
+__global__ void k_comm_fill(int32_t n, const int32_t *Cp, const int32_t *coff, int32_t *cursor,
+                            int32_t *members)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = Cp[i];
+        const int pos = atomicAdd(&cursor[c], 1);
+        members[coff[c] + pos] = (int32_t)i;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+int64_t scan_scratch_elems(int64_t n) { return (n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1; }
+
+template <typename TI, typename TO>
+void launch_exclusive_scan(const TI *in, TO *out, int64_t n, int64_t *scratch,
+                           unsigned long long *total, hipStream_t s)
+{
+    const int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (nb > 0) k_scan_reduce<TI><<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, n, scratch);
+    k_scan_partials<TO><<<1, SCAN_THREADS, 0, s>>>(scratch, nb, out, n, total);
+    if (nb > 0) k_scan_apply<TI, TO><<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, out, n, scratch);
+}
+template void launch_exclusive_scan<int32_t, int32_t>(const int32_t *, int32_t *, int64_t,
+                                                      int64_t *, unsigned long long *,
+                                                      hipStream_t);
+template void launch_exclusive_scan<int64_t, int64_t>(const int64_t *, int64_t *, int64_t,
+                                                      int64_t *, unsigned long long *,
+                                                      hipStream_t);
+
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
+{
+    if (n > 0) k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+}
+
+void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s)
+{
+    if (n > 0) k_fill_u8<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+}
+
+void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s)
+{
+    // bytes is a multiple of 8 for every caller (regions are 256-byte aligned)
+    const int64_t n = bytes / 8;
+    if (n > 0) k_zero_u64<<<grid_for(n, 256), 256, 0, s>>>((unsigned long long *)p, n);
+}
+
+void launch_iota(int32_t *p, int64_t n, hipStream_t s)
+{
+    if (n > 0) k_iota<<<grid_for(n, 256), 256, 0, s>>>(p, n);
+}
+
+void launch_init_hash_slab(int32_t *keys, void *vals, int64_t slots, int vbytes, hipStream_t s)
+{
+    if (slots > 0)
+        k_init_slab<<<grid_for(slots, 256), 256, 0, s>>>(keys, (unsigned char *)vals, slots, vbytes);
+}
+
+void launch_validate(int32_t n, int64_t nnz, const int32_t *off, const int32_t *tgt,
+                     const int32_t *w, int32_t *err, unsigned long long *W, hipStream_t s)
+{
+    const int64_t m = nnz > n ? nnz : n;
+    k_validate<<<grid_for(m + 1, 256), 256, 0, s>>>(n, nnz, off, tgt, w, err, W);
+}
+
+void launch_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,
+                          void *K, void *Sig, int sbytes, hipStream_t s)
+{
+    if (n > 0)
+        k_init_vertices<<<grid_for(n, 256), 256, 0, s>>>(n, Cp, size, fa, fb, (unsigned char *)K,
+                                                         (unsigned char *)Sig, sbytes);
+}
+
+void launch_bin_count(int32_t n, const int32_t *off, const int32_t *deg, int32_t *totals,
+                      hipStream_t s)
+{
+    if (n > 0) k_bin_count<<<grid_for(n, 256, 2048), 256, 0, s>>>(n, off, deg, totals);
+}
+
+void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, BinInfo bins,
+                     int32_t *cursors, int32_t *binorder, hipStream_t s)
+{
+    if (n > 0)
+        k_bin_fill<<<grid_for(n, 256, 2048), 256, 0, s>>>(n, off, deg, bins, cursors, binorder);
+}
+
+void launch_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
+                      const int32_t *deg, int64_t cap, int64_t *out, hipStream_t s)
+{
+    if (he > hb)
+        k_hub_sizes<<<grid_for(he - hb, 256), 256, 0, s>>>(binorder, hb, he, off, deg, cap, out);
+}
+
+template <class C>
+void launch_row_reduce(int bin, int op, const RowArgs<C> &a, hipStream_t s)
+{
+    if (a.count <= 0) return;
+    const int rows_per_block[NBINS] = {32, 8, 4, 4, 1, 1};
+    const int grid = grid_for(a.count, rows_per_block[bin], 4096);
+#define LV_ROW(G)                                                            \
+    do {                                                                     \
+        if (op == 0)                                                         \
+            k_row_reduce<C, G, 0><<<grid, 256, 0, s>>>(a);                   \
+        else                                                                 \
+            k_row_reduce<C, G, 1><<<grid, 256, 0, s>>>(a);                   \
+    } while (0)
+    switch (bin) {
+    case 0: LV_ROW(8); break;
+    case 1: LV_ROW(32); break;
+    case 2:
+    case 3: LV_ROW(64); break;
+    default: LV_ROW(256); break;
+    }
+#undef LV_ROW
+}
+template void launch_row_reduce<CfgNarrow>(int, int, const RowArgs<CfgNarrow> &, hipStream_t);
+template void launch_row_reduce<CfgWideIn>(int, int, const RowArgs<CfgWideIn> &, hipStream_t);
+template void launch_row_reduce<CfgWide>(int, int, const RowArgs<CfgWide> &, hipStream_t);
+
+template <typename ST>
+void launch_sum_squares(const ST *Sig, int32_t n, unsigned long long *acc, hipStream_t s)
+{
+    if (n > 0) k_sum_squares<ST><<<grid_for(n, 256, 2048), 256, 0, s>>>(Sig, n, acc);
+}
+template void launch_sum_squares<int32_t>(const int32_t *, int32_t, unsigned long long *,
+                                          hipStream_t);
+template void launch_sum_squares<int64_t>(const int64_t *, int32_t, unsigned long long *,
+                                          hipStream_t);
+
+void launch_compact(const CompactArgs &a, hipStream_t s)
+{
+    if (a.nb > 0) k_compact<<<grid_for(a.nb, 256, 4096), 256, 0, s>>>(a);
+}
+
+template <typename ST>
+void launch_apply(const int32_t *mv_v, const int32_t *mv_c, const int32_t *mv_count, int32_t *Cp,
+                  const ST *K, ST *Sig, int32_t *size, int32_t cap, const int32_t *done,
+                  hipStream_t s)
+{
+    if (cap > 0)
+        k_apply<ST><<<grid_for(cap, 256, 2048), 256, 0, s>>>(mv_v, mv_c, mv_count, Cp, K, Sig,
+                                                             size, cap, done);
+}
+template void launch_apply<int32_t>(const int32_t *, const int32_t *, const int32_t *, int32_t *,
+                                    const int32_t *, int32_t *, int32_t *, int32_t,
+                                    const int32_t *, hipStream_t);
+template void launch_apply<int64_t>(const int32_t *, const int32_t *, const int32_t *, int32_t *,
+                                    const int64_t *, int64_t *, int32_t *, int32_t,
+                                    const int32_t *, hipStream_t);
+
+void launch_round_end(DevScalars *sc, int it, hipStream_t s)
+{
+    k_round_end<<<1, 64, 0, s>>>(sc, it);
+}
+
+void launch_iter_end(DevScalars *sc, int it, double tau, hipStream_t s)
+{
+    k_iter_end<<<1, 64, 0, s>>>(sc, it, tau);
+}
+
+void launch_mark_used(int32_t n, const int32_t *labels, int32_t *used, hipStream_t s)
+{
+    if (n > 0) k_mark_used<<<grid_for(n, 256), 256, 0, s>>>(n, labels, used);
+}
+
+void launch_relabel(int32_t n, int32_t *labels, const int32_t *map, hipStream_t s)
+{
+    if (n > 0) k_relabel<<<grid_for(n, 256), 256, 0, s>>>(n, labels, map);
+}
+
+void launch_comm_count(int32_t n, const int32_t *Cp, const int32_t *off, const int32_t *deg,
+                       int32_t *ccount, int32_t *ctot, hipStream_t s)
+{
+    if (n > 0) k_comm_count<<<grid_for(n, 256), 256, 0, s>>>(n, Cp, off, deg, ccount, ctot);
+}
+
+void launch_comm_fill(int32_t n, const int32_t *Cp, const int32_t *coff, int32_t *cursor,
+                      int32_t *members, hipStream_t s)
+{
+    if (n > 0) k_comm_fill<<<grid_for(n, 256), 256, 0, s>>>(n, Cp, coff, cursor, members);
+}
+
+}  // namespace lv

@@ -1,0 +1,155 @@
+// Launchers of the gfx950 Louvain kernels (internal to the library).
+#pragma once
+
+#include "common.h"
+
+namespace lv {
+
+// Bin boundaries of one level: bin b holds binorder[start[b] .. start[b+1]).
+struct BinInfo {
+    int32_t start[NBINS + 1];
+};
+
+// ----------------------------------------------------------------- scans
+// Exclusive prefix sum of in[0..n) into out[0..n], out[n] = total; the total
+// is also stored in *total (device).  Scratch needs scan_scratch_elems(n)
+// int64 elements.
+int64_t scan_scratch_elems(int64_t n);
+template <typename TI, typename TO>
+void launch_exclusive_scan(const TI *in, TO *out, int64_t n, int64_t *scratch,
+                           unsigned long long *total, hipStream_t s);
+
+// ----------------------------------------------------------------- fills / setup
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s);
+void launch_iota(int32_t *p, int64_t n, hipStream_t s);
+void launch_init_hash_slab(int32_t *keys, void *vals, int64_t slots, int vbytes, hipStream_t s);
+
+// Validation of the input CSR; sets bits of *err and adds weights into *W.
+void launch_validate(int32_t n, int64_t nnz, const int32_t *off, const int32_t *tgt,
+                     const int32_t *w, int32_t *err, unsigned long long *W, hipStream_t s);
+
+// Per-level reset: C' = iota, size = 1, flagsA = 1, flagsB = 0, K = Sigma = 0.
+void launch_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,
+                          void *K, void *Sig, int sbytes, hipStream_t s);
+
+// Degree binning: count rows per bin into totals[0..NBINS), then fill binorder.
+// Row length: deg[v] if deg, else off[v+1]-off[v].
+void launch_bin_count(int32_t n, const int32_t *off, const int32_t *deg, int32_t *totals,
+                      hipStream_t s);
+void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, BinInfo bins,
+                     int32_t *cursors, int32_t *binorder, hipStream_t s);
+
+// HBM table sizes of the rows binorder[hb .. he): out[p-hb] = hub_slots(len),
+// len capped at cap (aggregation caps a community's table at |Gamma|).
+void launch_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
+                      const int32_t *deg, int64_t cap, int64_t *out, hipStream_t s);
+
+// Row reductions over the rows of one bin.
+//   op 0: K[v] = Sigma[v] = sum of row weights
+//   op 1: *sigma += sum of row weights whose target has the same label
+template <class C>
+struct RowArgs {
+    const int32_t *off, *deg, *tgt;
+    const typename C::WT *w;
+    const int32_t *binorder;
+    int32_t begin, count;
+    typename C::ST *K, *Sig;
+    const int32_t *labels;
+    unsigned long long *sigma;
+};
+template <class C>
+void launch_row_reduce(int bin, int op, const RowArgs<C> &a, hipStream_t s);
+
+// Sum of Sigma_c^2 (128-bit) over c < n into acc[2].
+template <typename ST>
+void launch_sum_squares(const ST *Sig, int32_t n, unsigned long long *acc, hipStream_t s);
+
+// ----------------------------------------------------------------- local moving
+struct CompactArgs {
+    const int32_t *binorder;
+    int32_t nb;  // rows in bins (binorder[0..nb))
+    BinInfo bins;
+    uint8_t *flags;  // active flags of this iteration (cleared as they are taken)
+    int32_t prune;
+    int32_t round, round_bits, pass, it;
+    uint64_t seed;
+    int32_t *worklist;  // positions into binorder, grouped by bin at bins.start[b]
+    int32_t *counts;    // per-bin count of this round (zero on entry)
+    const int32_t *done;
+};
+void launch_compact(const CompactArgs &a, hipStream_t s);
+
+template <class C>
+struct MoveArgs {
+    const int32_t *off, *deg, *tgt;
+    const typename C::WT *w;
+    const int32_t *binorder, *worklist;
+    int32_t list_begin;
+    const int32_t *count;
+    int32_t *Cp;
+    const typename C::ST *K;
+    typename C::ST *Sig;
+    int32_t *size;
+    uint8_t *flags_next;
+    int32_t *mv_v, *mv_c, *mv_count;   // deferred moves (deterministic mode)
+    int32_t *hkeys;                    // HBM tables of the hub bin
+    typename C::ST *hvals;
+    const int64_t *hoff;
+    unsigned long long *sumN;          // 128-bit gain sum of this iteration
+    unsigned long long *work;          // [vertices, entries, keys, moves]
+    unsigned long long *it_moves, *it_scanned;
+    const int32_t *done;
+    int64_t W;
+    int32_t rule;                      // min-label rule for singleton moves
+};
+// grid: workgroups to launch for this bin (each loops over the device count)
+template <class C>
+void launch_move(int bin, bool fast, const MoveArgs<C> &a, int grid, hipStream_t s);
+int move_rows_per_block(int bin);
+
+// Deferred moves of a round (deterministic mode).
+template <typename ST>
+void launch_apply(const int32_t *mv_v, const int32_t *mv_c, const int32_t *mv_count, int32_t *Cp,
+                  const ST *K, ST *Sig, int32_t *size, int32_t cap, const int32_t *done,
+                  hipStream_t s);
+
+// End of a round: processed += counts, counts = 0, mv_count = 0.
+void launch_round_end(DevScalars *sc, int it, hipStream_t s);
+// End of an iteration: delta-Q test against tau, done / iters update.
+void launch_iter_end(DevScalars *sc, int it, double tau, hipStream_t s);
+
+// ----------------------------------------------------------------- aggregation
+void launch_mark_used(int32_t n, const int32_t *labels, int32_t *used, hipStream_t s);
+void launch_relabel(int32_t n, int32_t *labels, const int32_t *map, hipStream_t s);
+void launch_comm_count(int32_t n, const int32_t *Cp, const int32_t *off, const int32_t *deg,
+                       int32_t *ccount, int32_t *ctot, hipStream_t s);
+void launch_comm_fill(int32_t n, const int32_t *Cp, const int32_t *coff, int32_t *cursor,
+                      int32_t *members, hipStream_t s);
+
+template <class C>
+struct AggArgs {
+    const int32_t *off, *deg, *tgt;   // level G'
+    const typename C::WT *w;
+    const int32_t *Cp;                // dense labels of G'
+    const int32_t *coff, *members;    // community-vertex CSR
+    const int32_t *cbinorder;         // communities grouped by bin
+    int32_t begin, count;             // this bin's segment of cbinorder
+    const int32_t *yoff;              // holey offsets of G''
+    int32_t *ydeg;                    // used length of each row of G''
+    int32_t *ytgt;
+    typename C::ST *yw;
+    int32_t *hkeys;
+    typename C::ST *hvals;
+    const int64_t *hoff;
+    unsigned long long *work;         // [communities, members, entries, emitted]
+};
+// Bins 0-4 (LDS tables); the hub bin goes through launch_aggregate_hub.
+template <class C>
+void launch_aggregate(int bin, const AggArgs<C> &a, hipStream_t s);
+// Bin 5: HBM tables of hub_slots(min(total degree, ncomm)) slots at hoff[index in bin].
+template <class C>
+void launch_aggregate_hub(const AggArgs<C> &a, int32_t ncomm, hipStream_t s);
+
+}  // namespace lv

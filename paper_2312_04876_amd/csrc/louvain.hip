@@ -1,0 +1,1011 @@
+// Host side of the C ABI: context, workspace layout, the pass loop of Alg. 1
+// around the local-moving (Alg. 2) and aggregation (Alg. 3) kernels.
+//
+// Control stays on the device within a pass: every iteration ends with a
+// one-thread kernel that applies the tolerance test of Alg. 2 and raises a
+// done flag that all later kernels of the pass check, so the host enqueues
+// iterations ahead and only reads the flag one iteration behind.  The host
+// synchronises once per level (degree-bin sizes), once per pass (community
+// count for the aggregation tolerance of Alg. 1) and once for the community
+// bins of the aggregation.
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace lv;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+struct Layout {
+    size_t total;
+    int sb;  // bytes of K', Sigma', table values and aggregated weights (4 or 8)
+    int64_t slots, scratch_elems;
+    size_t scalars, Cp, top, K, Sig, size, fa, fb, binorder, worklist, mv_v, mv_c;
+    size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
+    size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
+    size_t hkeys, hvals, hsz, hoff, scratch;
+};
+
+Layout make_layout(int32_t n, int64_t nnz, int sb)
+{
+    Layout L;
+    memset(&L, 0, sizeof(L));
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = cur;
+        cur += (bytes + ALIGN - 1) / ALIGN * ALIGN;
+        return o;
+    };
+    const size_t n1 = (size_t)n + 1;
+    const size_t z = (size_t)(nnz > 0 ? nnz : 1);
+    L.sb = sb;
+    L.slots = 2 * (int64_t)z + (int64_t)z / 64 + 1024;
+    L.scratch_elems = scan_scratch_elems((int64_t)n1);
+    L.scalars = take(sizeof(DevScalars));
+    L.Cp = take(4 * n1);
+    L.top = take(4 * n1);
+    L.K = take((size_t)sb * n1);
+    L.Sig = take((size_t)sb * n1);
+    L.size = take(4 * n1);
+    L.fa = take(n1);
+    L.fb = take(n1);
+    L.binorder = take(4 * n1);
+    L.worklist = take(4 * n1);
+    L.mv_v = take(4 * n1);
+    L.mv_c = take(4 * n1);
+    L.used = take(4 * (n1 + 1));
+    L.idmap = take(4 * (n1 + 1));
+    L.ccount = take(4 * (n1 + 1));
+    L.coff = take(4 * (n1 + 1));
+    L.ctot = take(4 * (n1 + 1));
+    L.cursor = take(4 * n1);
+    L.members = take(4 * n1);
+    L.cbinorder = take(4 * n1);
+    L.offA = take(4 * (n1 + 1));
+    L.offB = take(4 * (n1 + 1));
+    L.degA = take(4 * n1);
+    L.degB = take(4 * n1);
+    L.tgtA = take(4 * z);
+    L.tgtB = take(4 * z);
+    L.wA = take((size_t)sb * z);
+    L.wB = take((size_t)sb * z);
+    L.hkeys = take(4 * (size_t)L.slots);
+    L.hvals = take((size_t)sb * (size_t)L.slots);
+    L.hsz = take(8 * (n1 + 1));
+    L.hoff = take(8 * (n1 + 1));
+    L.scratch = take(8 * (size_t)L.scratch_elems);
+    L.total = cur;
+    return L;
+}
+
+enum State { S_READY = 0, S_MOVED = 1, S_STOPPED = 2, S_EXHAUSTED = 3, S_DONE = 4 };
+
+struct LevelH {
+    int32_t n;
+    const int32_t *off, *deg, *tgt;
+    const void *w;
+    int wbytes;
+    int buf;  // -1 input, 0 = A, 1 = B
+    int64_t entries;
+};
+
+// Kernel families timed with HIP events when profiling.
+enum Fam {
+    F_MOVE0 = 0,  // .. F_MOVE0 + 5
+    F_AGG0 = 6,   // .. F_AGG0 + 5
+    F_COMPACT = 12,
+    F_APPLY,
+    F_ITER,
+    F_SETUP,
+    F_AGGPREP,
+    F_FINAL,
+    F_COUNT
+};
+const char *FAM_NAMES[F_COUNT] = {
+    "move_bin0_8lanes", "move_bin1_32lanes", "move_bin2_wave", "move_bin3_wave",
+    "move_bin4_block", "move_bin5_hub", "agg_bin0_8lanes", "agg_bin1_32lanes",
+    "agg_bin2_wave", "agg_bin3_wave", "agg_bin4_block", "agg_bin5_hub",
+    "compact", "apply", "iteration_end", "level_setup", "aggregate_prep", "final"};
+
+struct Pending {
+    int fam;
+    hipEvent_t a, b;
+};
+
+const char *g_last_hip_error = "no HIP error";
+
+}  // namespace
+
+struct louvain_ctx {
+    louvain_params p;
+    hipStream_t s;
+    int32_t n;
+    int64_t nnz;
+    const int32_t *in_off, *in_tgt, *in_w;
+    unsigned char *ws;
+    Layout L;
+    DevScalars *sc;
+    DevScalars *hsc;  // pinned host copy
+    int32_t *pinned_done;
+    hipEvent_t it_ev[2];
+    int32_t *Cp, *top, *size, *binorder, *worklist, *mv_v, *mv_c;
+    int32_t *used, *idmap, *ccount, *coff, *ctot, *cursor, *members, *cbinorder;
+    uint8_t *fa, *fb;
+    void *K, *Sig;
+    int32_t *off_buf[2], *deg_buf[2], *tgt_buf[2];
+    void *w_buf[2];
+    int32_t *hkeys;
+    void *hvals;
+    int64_t *hsz, *hoff, *scratch;
+    int64_t W;
+    bool wide;
+    int state;
+    int pass;
+    double tau;
+    int32_t iters_last;
+    double dq_last;
+    LevelH lev;
+    BinInfo bins;
+    int32_t nb;
+    louvain_stats st;
+    // per-iteration trace of the last move
+    std::vector<i128> tr_sum;
+    std::vector<int64_t> tr_moves, tr_proc;
+    // profiling
+    std::vector<hipEvent_t> ev_free;
+    std::vector<Pending> pending;
+    double fam_ms[F_COUNT];
+    int64_t fam_launches[F_COUNT];
+    double fam_bytes[F_COUNT];
+    hipError_t last_err;
+};
+
+namespace {
+
+#define CK(x)                                                   \
+    do {                                                        \
+        hipError_t e_ = (x);                                    \
+        if (e_ != hipSuccess) {                                 \
+            ctx->last_err = e_;                                 \
+            g_last_hip_error = hipGetErrorString(e_);           \
+            return LOUVAIN_EHIP;                                \
+        }                                                       \
+    } while (0)
+
+#define CKL() CK(hipGetLastError())
+
+#define TRY(x)                          \
+    do {                                \
+        int r_ = (x);                   \
+        if (r_ != LOUVAIN_OK) return r_; \
+    } while (0)
+
+int bins_of(louvain_ctx *ctx, int b) { return ctx->bins.start[b + 1] - ctx->bins.start[b]; }
+
+// ---------------------------------------------------------------- profiling
+int prof_begin(louvain_ctx *ctx, hipEvent_t *ev)
+{
+    *ev = nullptr;
+    if (!ctx->p.profile) return LOUVAIN_OK;
+    if (ctx->ev_free.empty()) {
+        hipEvent_t e;
+        CK(hipEventCreate(&e));
+        ctx->ev_free.push_back(e);
+    }
+    *ev = ctx->ev_free.back();
+    ctx->ev_free.pop_back();
+    CK(hipEventRecord(*ev, ctx->s));
+    return LOUVAIN_OK;
+}
+
+int prof_end(louvain_ctx *ctx, int fam, hipEvent_t a)
+{
+    if (!ctx->p.profile || !a) return LOUVAIN_OK;
+    hipEvent_t b;
+    if (ctx->ev_free.empty()) {
+        CK(hipEventCreate(&b));
+    } else {
+        b = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+    }
+    CK(hipEventRecord(b, ctx->s));
+    ctx->pending.push_back(Pending{fam, a, b});
+    return LOUVAIN_OK;
+}
+
+// Called after the stream has been synchronised.
+int prof_collect(louvain_ctx *ctx)
+{
+    for (const Pending &q : ctx->pending) {
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, q.a, q.b));
+        ctx->fam_ms[q.fam] += ms;
+        ctx->fam_launches[q.fam] += 1;
+        ctx->ev_free.push_back(q.a);
+        ctx->ev_free.push_back(q.b);
+    }
+    ctx->pending.clear();
+    return LOUVAIN_OK;
+}
+
+int sync_stream(louvain_ctx *ctx)
+{
+    CK(hipStreamSynchronize(ctx->s));
+    return prof_collect(ctx);
+}
+
+int read_scalars(louvain_ctx *ctx)
+{
+    CK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->s));
+    return sync_stream(ctx);
+}
+
+template <class C>
+const typename C::WT *lev_w(const LevelH &l)
+{
+    return (const typename C::WT *)l.w;
+}
+
+// ---------------------------------------------------------------- level setup (Alg. 1 per-pass reset)
+template <class C>
+int setup_level(louvain_ctx *ctx)
+{
+    hipStream_t s = ctx->s;
+    const LevelH &l = ctx->lev;
+    hipEvent_t ev;
+    TRY(prof_begin(ctx, &ev));
+    launch_fill_bytes_zero(ctx->sc, offsetof(DevScalars, err), s);
+    CKL();
+    launch_init_vertices(l.n, ctx->Cp, ctx->size, ctx->fa, ctx->fb, ctx->K, ctx->Sig, ctx->L.sb, s);
+    launch_bin_count(l.n, l.off, l.deg, ctx->sc->bin_total, s);
+    CKL();
+    TRY(prof_end(ctx, F_SETUP, ev));
+    TRY(read_scalars(ctx));
+    ctx->bins.start[0] = 0;
+    for (int b = 0; b < NBINS; ++b) ctx->bins.start[b + 1] = ctx->bins.start[b] + ctx->hsc->bin_total[b];
+    ctx->nb = ctx->bins.start[NBINS];
+    TRY(prof_begin(ctx, &ev));
+    launch_bin_fill(l.n, l.off, l.deg, ctx->bins, ctx->sc->bin_cursor, ctx->binorder, s);
+    CKL();
+    const int hubs = bins_of(ctx, NBINS - 1);
+    if (hubs > 0) {
+        launch_hub_sizes(ctx->binorder, ctx->bins.start[NBINS - 1], ctx->bins.start[NBINS], l.off,
+                         l.deg, INT64_MAX, ctx->hsz, s);
+        launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
+        CKL();
+    }
+    for (int b = 0; b < NBINS; ++b) {
+        RowArgs<C> r;
+        r.off = l.off;
+        r.deg = l.deg;
+        r.tgt = l.tgt;
+        r.w = lev_w<C>(l);
+        r.binorder = ctx->binorder;
+        r.begin = ctx->bins.start[b];
+        r.count = bins_of(ctx, b);
+        r.K = (typename C::ST *)ctx->K;
+        r.Sig = (typename C::ST *)ctx->Sig;
+        r.labels = nullptr;
+        r.sigma = nullptr;
+        launch_row_reduce<C>(b, 0, r, s);
+        CKL();
+    }
+    TRY(prof_end(ctx, F_SETUP, ev));
+    return LOUVAIN_OK;
+}
+
+// ---------------------------------------------------------------- local moving (Alg. 2)
+template <class C>
+int move_phase(louvain_ctx *ctx)
+{
+    typedef typename C::ST ST;
+    hipStream_t s = ctx->s;
+    const LevelH &l = ctx->lev;
+    TRY(setup_level<C>(ctx));
+    const bool fast = ctx->p.mode == LOUVAIN_FAST;
+    const int rounds = 1 << ctx->p.round_bits;
+    const int max_it = ctx->p.max_iterations;
+    MoveArgs<C> a;
+    a.off = l.off;
+    a.deg = l.deg;
+    a.tgt = l.tgt;
+    a.w = lev_w<C>(l);
+    a.binorder = ctx->binorder;
+    a.worklist = ctx->worklist;
+    a.Cp = ctx->Cp;
+    a.K = (const ST *)ctx->K;
+    a.Sig = (ST *)ctx->Sig;
+    a.size = ctx->size;
+    a.mv_v = ctx->mv_v;
+    a.mv_c = ctx->mv_c;
+    a.mv_count = &ctx->sc->mv_count;
+    a.hkeys = ctx->hkeys;
+    a.hvals = (ST *)ctx->hvals;
+    a.hoff = ctx->hoff;
+    a.done = &ctx->sc->done;
+    a.W = ctx->W;
+    a.rule = 1;
+    int grid[NBINS];
+    for (int b = 0; b < NBINS; ++b) {
+        const int cnt = bins_of(ctx, b);
+        const int per = move_rows_per_block(b);
+        int g = (cnt + per - 1) / per;
+        const int cap = b >= 4 ? 1024 : 2048;
+        grid[b] = std::min(g, cap);
+    }
+    int it;
+    for (it = 0; it < max_it; ++it) {
+        uint8_t *cur = (it & 1) ? ctx->fb : ctx->fa;
+        uint8_t *nxt = (it & 1) ? ctx->fa : ctx->fb;
+        a.flags_next = nxt;
+        a.sumN = ctx->sc->sumN[it];
+        a.it_moves = &ctx->sc->moves[it];
+        a.it_scanned = &ctx->sc->scanned[it];
+        for (int r = 0; r < rounds; ++r) {
+            CompactArgs ca;
+            ca.binorder = ctx->binorder;
+            ca.nb = ctx->nb;
+            ca.bins = ctx->bins;
+            ca.flags = cur;
+            ca.prune = ctx->p.prune;
+            ca.round = r;
+            ca.round_bits = ctx->p.round_bits;
+            ca.pass = ctx->pass;
+            ca.it = it;
+            ca.seed = ctx->p.seed;
+            ca.worklist = ctx->worklist;
+            ca.counts = ctx->sc->bin_count;
+            ca.done = &ctx->sc->done;
+            hipEvent_t ev;
+            TRY(prof_begin(ctx, &ev));
+            launch_compact(ca, s);
+            CKL();
+            TRY(prof_end(ctx, F_COMPACT, ev));
+            for (int b = 0; b < NBINS; ++b) {
+                if (grid[b] <= 0) continue;
+                a.list_begin = ctx->bins.start[b];
+                a.count = &ctx->sc->bin_count[b];
+                a.work = ctx->sc->work[WORK_MOVE + b];
+                TRY(prof_begin(ctx, &ev));
+                launch_move<C>(b, fast, a, grid[b], s);
+                CKL();
+                TRY(prof_end(ctx, F_MOVE0 + b, ev));
+            }
+            TRY(prof_begin(ctx, &ev));
+            if (!fast) {
+                launch_apply<ST>(ctx->mv_v, ctx->mv_c, &ctx->sc->mv_count, ctx->Cp, (const ST *)ctx->K,
+                                 (ST *)ctx->Sig, ctx->size, ctx->nb, &ctx->sc->done, s);
+                CKL();
+            }
+            launch_round_end(ctx->sc, it, s);
+            CKL();
+            TRY(prof_end(ctx, F_APPLY, ev));
+        }
+        hipEvent_t ev;
+        TRY(prof_begin(ctx, &ev));
+        launch_iter_end(ctx->sc, it, ctx->tau, s);
+        CKL();
+        TRY(prof_end(ctx, F_ITER, ev));
+        CK(hipMemcpyAsync(&ctx->pinned_done[it], &ctx->sc->done, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+        CK(hipEventRecord(ctx->it_ev[it & 1], s));
+        // look one iteration behind so the device always has queued work
+        if (it >= 1) {
+            CK(hipEventSynchronize(ctx->it_ev[(it - 1) & 1]));
+            if (ctx->pinned_done[it - 1]) break;
+        }
+    }
+    TRY(read_scalars(ctx));
+    const DevScalars &h = *ctx->hsc;
+    ctx->iters_last = h.iters;
+    ctx->dq_last = h.iters > 0 ? h.dq[h.iters - 1] : 0.0;
+    ctx->tr_sum.assign(h.iters, 0);
+    ctx->tr_moves.assign(h.iters, 0);
+    ctx->tr_proc.assign(h.iters, 0);
+    int64_t mv = 0, pr = 0, scn = 0;
+    for (int k = 0; k < h.iters; ++k) {
+        ctx->tr_sum[k] = join_i128(h.sumN[k][0], h.sumN[k][1]);
+        ctx->tr_moves[k] = (int64_t)h.moves[k];
+        ctx->tr_proc[k] = (int64_t)h.processed[k];
+        mv += (int64_t)h.moves[k];
+        pr += (int64_t)h.processed[k];
+        scn += (int64_t)h.scanned[k];
+    }
+    const int P = ctx->pass;
+    if (P < LOUVAIN_MAX_PASSES) {
+        ctx->st.passes = P + 1;
+        ctx->st.iterations[P] = h.iters;
+        ctx->st.vertices[P] = l.n;
+        ctx->st.entries[P] = l.entries;
+        ctx->st.dq_last[P] = ctx->dq_last;
+        ctx->st.moves[P] = mv;
+        ctx->st.processed[P] = pr;
+        ctx->st.scanned[P] = scn;
+    }
+    return LOUVAIN_OK;
+}
+
+// Dense order-preserving renumbering of labels[0..n) (values < range) in place.
+int renumber_dense(louvain_ctx *ctx, int32_t *labels, int32_t n, int32_t range)
+{
+    hipStream_t s = ctx->s;
+    launch_fill_i32(ctx->used, 0, (int64_t)range + 1, s);
+    launch_mark_used(n, labels, ctx->used, s);
+    launch_exclusive_scan<int32_t, int32_t>(ctx->used, ctx->idmap, range, ctx->scratch,
+                                            &ctx->sc->scan_total, s);
+    launch_relabel(n, labels, ctx->idmap, s);
+    CKL();
+    return LOUVAIN_OK;
+}
+
+// ---------------------------------------------------------------- aggregation (Alg. 1 tail + Alg. 3)
+template <class C>
+int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
+{
+    typedef typename C::ST ST;
+    hipStream_t s = ctx->s;
+    const LevelH l = ctx->lev;
+    hipEvent_t ev;
+    TRY(prof_begin(ctx, &ev));
+    // number of communities |Gamma| after local moving
+    launch_fill_i32(ctx->used, 0, (int64_t)l.n + 1, s);
+    launch_mark_used(l.n, ctx->Cp, ctx->used, s);
+    launch_exclusive_scan<int32_t, int32_t>(ctx->used, ctx->idmap, l.n, ctx->scratch,
+                                            &ctx->sc->scan_total, s);
+    CKL();
+    TRY(prof_end(ctx, F_AGGPREP, ev));
+    TRY(read_scalars(ctx));
+    const int32_t nc = (int32_t)ctx->hsc->scan_total;
+    const int P = ctx->pass;
+    if (P < LOUVAIN_MAX_PASSES) ctx->st.communities[P] = nc;
+    if (communities) *communities = nc;
+    // Alg. 1: globally converged, or too few merges
+    if (ctx->iters_last <= 1 || (double)nc / (double)l.n > ctx->p.aggregation_tolerance) {
+        ctx->state = S_STOPPED;
+        if (stop) *stop = 1;
+        return LOUVAIN_OK;
+    }
+    const int nbuf = l.buf == 0 ? 1 : 0;
+    int32_t *yoff = ctx->off_buf[nbuf], *ydeg = ctx->deg_buf[nbuf], *ytgt = ctx->tgt_buf[nbuf];
+    ST *yw = (ST *)ctx->w_buf[nbuf];
+    TRY(prof_begin(ctx, &ev));
+    // renumber communities (prefix sum over used ids) and look up the dendrogram
+    launch_relabel(l.n, ctx->Cp, ctx->idmap, s);
+    launch_relabel(ctx->n, ctx->top, ctx->Cp, s);
+    // community-vertex CSR: count, exclusive scan, fill
+    launch_fill_i32(ctx->ccount, 0, (int64_t)nc + 1, s);
+    launch_fill_i32(ctx->ctot, 0, (int64_t)nc + 1, s);
+    launch_comm_count(l.n, ctx->Cp, l.off, l.deg, ctx->ccount, ctx->ctot, s);
+    launch_exclusive_scan<int32_t, int32_t>(ctx->ccount, ctx->coff, nc, ctx->scratch, nullptr, s);
+    launch_exclusive_scan<int32_t, int32_t>(ctx->ctot, yoff, nc, ctx->scratch, nullptr, s);
+    launch_fill_i32(ctx->cursor, 0, nc, s);
+    launch_comm_fill(l.n, ctx->Cp, ctx->coff, ctx->cursor, ctx->members, s);
+    // bins of communities by total degree
+    launch_fill_i32(ctx->sc->bin_total, 0, 8, s);
+    launch_fill_i32(ctx->sc->bin_cursor, 0, 8, s);
+    launch_bin_count(nc, nullptr, ctx->ctot, ctx->sc->bin_total, s);
+    launch_fill_i32(ydeg, 0, nc, s);
+    CKL();
+    TRY(prof_end(ctx, F_AGGPREP, ev));
+    TRY(read_scalars(ctx));
+    BinInfo cb;
+    cb.start[0] = 0;
+    for (int b = 0; b < NBINS; ++b) cb.start[b + 1] = cb.start[b] + ctx->hsc->bin_total[b];
+    TRY(prof_begin(ctx, &ev));
+    launch_bin_fill(nc, nullptr, ctx->ctot, cb, ctx->sc->bin_cursor, ctx->cbinorder, s);
+    const int hubs = cb.start[NBINS] - cb.start[NBINS - 1];
+    if (hubs > 0) {
+        launch_hub_sizes(ctx->cbinorder, cb.start[NBINS - 1], cb.start[NBINS], nullptr, ctx->ctot,
+                         nc, ctx->hsz, s);
+        launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
+    }
+    CKL();
+    TRY(prof_end(ctx, F_AGGPREP, ev));
+    unsigned long long emitted0 = 0;
+    for (int b = 0; b < NBINS; ++b) emitted0 += ctx->hsc->work[WORK_AGG + b][3];
+    AggArgs<C> g;
+    g.off = l.off;
+    g.deg = l.deg;
+    g.tgt = l.tgt;
+    g.w = lev_w<C>(l);
+    g.Cp = ctx->Cp;
+    g.coff = ctx->coff;
+    g.members = ctx->members;
+    g.cbinorder = ctx->cbinorder;
+    g.yoff = yoff;
+    g.ydeg = ydeg;
+    g.ytgt = ytgt;
+    g.yw = yw;
+    g.hkeys = ctx->hkeys;
+    g.hvals = (ST *)ctx->hvals;
+    g.hoff = ctx->hoff;
+    for (int b = 0; b < NBINS; ++b) {
+        g.begin = cb.start[b];
+        g.count = cb.start[b + 1] - cb.start[b];
+        if (g.count <= 0) continue;
+        g.work = ctx->sc->work[WORK_AGG + b];
+        TRY(prof_begin(ctx, &ev));
+        if (b < NBINS - 1)
+            launch_aggregate<C>(b, g, s);
+        else
+            launch_aggregate_hub<C>(g, nc, s);
+        CKL();
+        TRY(prof_end(ctx, F_AGG0 + b, ev));
+    }
+    // the super-vertex graph becomes the next level (Alg. 1: G' <- G'')
+    TRY(read_scalars(ctx));
+    unsigned long long emitted1 = 0;
+    for (int b = 0; b < NBINS; ++b) emitted1 += ctx->hsc->work[WORK_AGG + b][3];
+    LevelH nl;
+    nl.n = nc;
+    nl.off = yoff;
+    nl.deg = ydeg;
+    nl.tgt = ytgt;
+    nl.w = yw;
+    nl.wbytes = ctx->L.sb;
+    nl.buf = nbuf;
+    nl.entries = (int64_t)(emitted1 - emitted0);
+    ctx->lev = nl;
+    ctx->tau = ctx->tau / ctx->p.tolerance_drop;
+    ctx->pass += 1;
+    const bool more = ctx->pass < ctx->p.max_passes;
+    ctx->state = more ? S_READY : S_EXHAUSTED;
+    if (stop) *stop = more ? 0 : 1;
+    return LOUVAIN_OK;
+}
+
+// Q of the current state (Eq. 1): on the last level with its labels (after an
+// early stop) or with singletons (after the last pass aggregated).
+template <class C>
+int modularity_t(louvain_ctx *ctx, double *q)
+{
+    typedef typename C::ST ST;
+    hipStream_t s = ctx->s;
+    if (ctx->state == S_EXHAUSTED) TRY(setup_level<C>(ctx));
+    const LevelH &l = ctx->lev;
+    hipEvent_t ev;
+    TRY(prof_begin(ctx, &ev));
+    launch_fill_bytes_zero(&ctx->sc->sigma, 3 * sizeof(unsigned long long), s);
+    for (int b = 0; b < NBINS; ++b) {
+        RowArgs<C> r;
+        r.off = l.off;
+        r.deg = l.deg;
+        r.tgt = l.tgt;
+        r.w = lev_w<C>(l);
+        r.binorder = ctx->binorder;
+        r.begin = ctx->bins.start[b];
+        r.count = bins_of(ctx, b);
+        r.K = nullptr;
+        r.Sig = nullptr;
+        r.labels = ctx->Cp;
+        r.sigma = &ctx->sc->sigma;
+        launch_row_reduce<C>(b, 1, r, s);
+    }
+    launch_sum_squares<ST>((const ST *)ctx->Sig, l.n, ctx->sc->s2, s);
+    CKL();
+    TRY(prof_end(ctx, F_FINAL, ev));
+    TRY(read_scalars(ctx));
+    const i128 sigma = (i128)ctx->hsc->sigma;
+    const i128 s2 = join_i128(ctx->hsc->s2[0], ctx->hsc->s2[1]);
+    const i128 W = (i128)ctx->W;
+    const i128 num = sigma * W - s2;
+    const i128 den = W * W;
+    *q = den == 0 ? 0.0 : i128_to_f64(num) / i128_to_f64(den);
+    return LOUVAIN_OK;
+}
+
+template <class C>
+int dispatch_move(louvain_ctx *ctx)
+{
+    return move_phase<C>(ctx);
+}
+
+int do_move(louvain_ctx *ctx)
+{
+    if (!ctx->wide) return move_phase<CfgNarrow>(ctx);
+    if (ctx->lev.buf < 0) return move_phase<CfgWideIn>(ctx);
+    return move_phase<CfgWide>(ctx);
+}
+
+int do_aggregate(louvain_ctx *ctx, int32_t *nc, int32_t *stop)
+{
+    if (!ctx->wide) return aggregate_phase<CfgNarrow>(ctx, nc, stop);
+    if (ctx->lev.buf < 0) return aggregate_phase<CfgWideIn>(ctx, nc, stop);
+    return aggregate_phase<CfgWide>(ctx, nc, stop);
+}
+
+int do_modularity(louvain_ctx *ctx, double *q)
+{
+    if (!ctx->wide) return modularity_t<CfgNarrow>(ctx, q);
+    if (ctx->lev.buf < 0) return modularity_t<CfgWideIn>(ctx, q);
+    return modularity_t<CfgWide>(ctx, q);
+}
+
+int check_params(const louvain_params *p)
+{
+    if (p->mode != LOUVAIN_DETERMINISTIC && p->mode != LOUVAIN_FAST) return LOUVAIN_EINVAL;
+    if (p->max_passes < 0 || p->max_passes > LOUVAIN_MAX_PASSES) return LOUVAIN_EINVAL;
+    if (p->max_iterations < 1 || p->max_iterations > LOUVAIN_MAX_ITERATIONS) return LOUVAIN_EINVAL;
+    if (p->round_bits < 0 || p->round_bits > 4) return LOUVAIN_EINVAL;
+    if (!(p->tolerance_drop > 0.0) || p->aggregation_tolerance != p->aggregation_tolerance ||
+        p->tolerance != p->tolerance)
+        return LOUVAIN_EINVAL;
+    return LOUVAIN_OK;
+}
+
+void reset_state(louvain_ctx *ctx)
+{
+    ctx->state = S_READY;
+    ctx->pass = 0;
+    ctx->tau = ctx->p.tolerance;
+    ctx->iters_last = 0;
+    ctx->dq_last = 0.0;
+    LevelH l;
+    l.n = ctx->n;
+    l.off = ctx->in_off;
+    l.deg = nullptr;
+    l.tgt = ctx->in_tgt;
+    l.w = ctx->in_w;
+    l.wbytes = 4;
+    l.buf = -1;
+    l.entries = ctx->nnz;
+    ctx->lev = l;
+    memset(&ctx->st, 0, sizeof(ctx->st));
+    ctx->tr_sum.clear();
+    ctx->tr_moves.clear();
+    ctx->tr_proc.clear();
+    if (ctx->p.max_passes == 0) ctx->state = S_EXHAUSTED;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+void louvain_default_params(louvain_params *p)
+{
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->mode = LOUVAIN_DETERMINISTIC;
+    p->max_passes = 10;
+    p->max_iterations = 20;
+    p->prune = 1;
+    p->tolerance = 0.01;
+    p->tolerance_drop = 10.0;
+    p->aggregation_tolerance = 0.8;
+    p->seed = 0;
+    p->round_bits = 1;
+    p->profile = 0;
+}
+
+int louvain_workspace_size(int32_t n, int64_t nnz, int64_t total_weight, const louvain_params *p,
+                           size_t *bytes)
+{
+    if (!bytes || n < 0 || nnz < 0) return LOUVAIN_EINVAL;
+    if (nnz > INT32_MAX) return LOUVAIN_EOVERFLOW;
+    if (p) {
+        const int r = check_params(p);
+        if (r) return r;
+    }
+    const int sb = (total_weight >= 0 && total_weight < ((int64_t)1 << 31)) ? 4 : 8;
+    *bytes = make_layout(n, nnz, sb).total;
+    return LOUVAIN_OK;
+}
+
+int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offsets,
+                 const int32_t *targets, const int32_t *weights, void *workspace,
+                 size_t workspace_bytes, const louvain_params *p, void *stream)
+{
+    if (!out) return LOUVAIN_EINVAL;
+    *out = nullptr;
+    if (n < 0 || nnz < 0 || !offsets || !workspace) return LOUVAIN_EINVAL;
+    if (nnz > 0 && (!targets || !weights)) return LOUVAIN_EINVAL;
+    if (nnz > INT32_MAX) return LOUVAIN_EOVERFLOW;
+    louvain_params prm;
+    if (p)
+        prm = *p;
+    else
+        louvain_default_params(&prm);
+    if (check_params(&prm)) return LOUVAIN_EINVAL;
+    const size_t need4 = make_layout(n, nnz, 4).total;
+    if (workspace_bytes < need4) return LOUVAIN_ENOSPC;
+
+    louvain_ctx *ctx = new (std::nothrow) louvain_ctx();
+    if (!ctx) return LOUVAIN_EINVAL;
+    ctx->p = prm;
+    ctx->s = (hipStream_t)stream;
+    ctx->n = n;
+    ctx->nnz = nnz;
+    ctx->in_off = offsets;
+    ctx->in_tgt = targets;
+    ctx->in_w = weights;
+    ctx->ws = (unsigned char *)workspace;
+    ctx->last_err = hipSuccess;
+    for (int f = 0; f < F_COUNT; ++f) {
+        ctx->fam_ms[f] = 0.0;
+        ctx->fam_launches[f] = 0;
+        ctx->fam_bytes[f] = 0.0;
+    }
+    auto fail = [&](int code) {
+        louvain_destroy(ctx);
+        return code;
+    };
+    if (hipHostMalloc((void **)&ctx->hsc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->pinned_done, sizeof(int32_t) * (LOUVAIN_MAX_ITERATIONS + 1),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->it_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->it_ev[1], hipEventDisableTiming) != hipSuccess) {
+        g_last_hip_error = "host-side allocation failed";
+        return fail(LOUVAIN_EHIP);
+    }
+    // validation and W with the narrow layout's scalar block (same offset in both layouts)
+    ctx->L = make_layout(n, nnz, 4);
+    ctx->sc = (DevScalars *)(ctx->ws + ctx->L.scalars);
+    launch_fill_bytes_zero(ctx->sc, sizeof(DevScalars), ctx->s);
+    launch_validate(n, nnz, offsets, targets, weights, &ctx->sc->err, &ctx->sc->W, ctx->s);
+    if (hipGetLastError() != hipSuccess) return fail(LOUVAIN_EHIP);
+    if (hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->s) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->s) != hipSuccess) {
+        g_last_hip_error = "validation kernel failed";
+        return fail(LOUVAIN_EHIP);
+    }
+    if (ctx->hsc->err) return fail(LOUVAIN_EINVAL);
+    const unsigned long long W = ctx->hsc->W;
+    if (W >= (1ull << 62)) return fail(LOUVAIN_EOVERFLOW);
+    ctx->W = (int64_t)W;
+    ctx->wide = W >= (1ull << 31);
+    ctx->L = make_layout(n, nnz, ctx->wide ? 8 : 4);
+    if (workspace_bytes < ctx->L.total) return fail(LOUVAIN_ENOSPC);
+    const Layout &L = ctx->L;
+    unsigned char *b = ctx->ws;
+    ctx->sc = (DevScalars *)(b + L.scalars);
+    ctx->Cp = (int32_t *)(b + L.Cp);
+    ctx->top = (int32_t *)(b + L.top);
+    ctx->K = b + L.K;
+    ctx->Sig = b + L.Sig;
+    ctx->size = (int32_t *)(b + L.size);
+    ctx->fa = b + L.fa;
+    ctx->fb = b + L.fb;
+    ctx->binorder = (int32_t *)(b + L.binorder);
+    ctx->worklist = (int32_t *)(b + L.worklist);
+    ctx->mv_v = (int32_t *)(b + L.mv_v);
+    ctx->mv_c = (int32_t *)(b + L.mv_c);
+    ctx->used = (int32_t *)(b + L.used);
+    ctx->idmap = (int32_t *)(b + L.idmap);
+    ctx->ccount = (int32_t *)(b + L.ccount);
+    ctx->coff = (int32_t *)(b + L.coff);
+    ctx->ctot = (int32_t *)(b + L.ctot);
+    ctx->cursor = (int32_t *)(b + L.cursor);
+    ctx->members = (int32_t *)(b + L.members);
+    ctx->cbinorder = (int32_t *)(b + L.cbinorder);
+    ctx->off_buf[0] = (int32_t *)(b + L.offA);
+    ctx->off_buf[1] = (int32_t *)(b + L.offB);
+    ctx->deg_buf[0] = (int32_t *)(b + L.degA);
+    ctx->deg_buf[1] = (int32_t *)(b + L.degB);
+    ctx->tgt_buf[0] = (int32_t *)(b + L.tgtA);
+    ctx->tgt_buf[1] = (int32_t *)(b + L.tgtB);
+    ctx->w_buf[0] = b + L.wA;
+    ctx->w_buf[1] = b + L.wB;
+    ctx->hkeys = (int32_t *)(b + L.hkeys);
+    ctx->hvals = b + L.hvals;
+    ctx->hsz = (int64_t *)(b + L.hsz);
+    ctx->hoff = (int64_t *)(b + L.hoff);
+    ctx->scratch = (int64_t *)(b + L.scratch);
+    // the scalar block keeps W; the hash slab starts empty and every user clears what it used
+    launch_init_hash_slab(ctx->hkeys, ctx->hvals, L.slots, L.sb, ctx->s);
+    launch_iota(ctx->top, n, ctx->s);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->s) != hipSuccess) {
+        g_last_hip_error = "workspace initialisation failed";
+        return fail(LOUVAIN_EHIP);
+    }
+    reset_state(ctx);
+    *out = ctx;
+    return LOUVAIN_OK;
+}
+
+int louvain_move(louvain_ctx *ctx, int32_t *iterations, double *delta_q)
+{
+    if (!ctx) return LOUVAIN_EINVAL;
+    if (ctx->state != S_READY) return LOUVAIN_ESTATE;
+    if (ctx->pass == 0) {
+        launch_iota(ctx->top, ctx->n, ctx->s);
+        CKL();
+    }
+    TRY(do_move(ctx));
+    ctx->state = S_MOVED;
+    if (iterations) *iterations = ctx->iters_last;
+    if (delta_q) *delta_q = ctx->dq_last;
+    return LOUVAIN_OK;
+}
+
+int louvain_aggregate(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
+{
+    if (!ctx) return LOUVAIN_EINVAL;
+    if (ctx->state != S_MOVED) return LOUVAIN_ESTATE;
+    return do_aggregate(ctx, communities, stop);
+}
+
+int louvain_run(louvain_ctx *ctx, int32_t *membership, double *modularity, louvain_stats *stats)
+{
+    if (!ctx || !membership) return LOUVAIN_EINVAL;
+    if (ctx->state == S_DONE) return LOUVAIN_ESTATE;
+    while (ctx->state == S_READY || ctx->state == S_MOVED) {
+        if (ctx->state == S_READY) TRY(louvain_move(ctx, nullptr, nullptr));
+        int32_t stop = 0;
+        TRY(louvain_aggregate(ctx, nullptr, &stop));
+    }
+    hipStream_t s = ctx->s;
+    if (ctx->state == S_STOPPED) {
+        // final dendrogram lookup (Alg. 1), only after an early stop
+        launch_relabel(ctx->n, ctx->top, ctx->Cp, s);
+        CKL();
+    }
+    double q = 0.0;
+    TRY(do_modularity(ctx, &q));
+    TRY(renumber_dense(ctx, ctx->top, ctx->n, ctx->lev.n > 0 ? ctx->lev.n : 1));
+    CK(hipMemcpyAsync(membership, ctx->top, sizeof(int32_t) * (size_t)ctx->n,
+                      hipMemcpyDeviceToDevice, s));
+    TRY(sync_stream(ctx));
+    ctx->state = S_DONE;
+    if (modularity) *modularity = q;
+    if (stats) *stats = ctx->st;
+    return LOUVAIN_OK;
+}
+
+int louvain_membership(louvain_ctx *ctx, int32_t *membership)
+{
+    if (!ctx || !membership) return LOUVAIN_EINVAL;
+    hipStream_t s = ctx->s;
+    CK(hipMemcpyAsync(membership, ctx->top, sizeof(int32_t) * (size_t)ctx->n,
+                      hipMemcpyDeviceToDevice, s));
+    if (ctx->state == S_MOVED || ctx->state == S_STOPPED) launch_relabel(ctx->n, membership, ctx->Cp, s);
+    CKL();
+    const int32_t range = ctx->state == S_DONE ? ctx->n : ctx->lev.n;
+    TRY(renumber_dense(ctx, membership, ctx->n, range > 0 ? range : 1));
+    TRY(sync_stream(ctx));
+    return LOUVAIN_OK;
+}
+
+int louvain_level_labels(louvain_ctx *ctx, int32_t *labels)
+{
+    if (!ctx || !labels) return LOUVAIN_EINVAL;
+    if (ctx->state != S_MOVED && ctx->state != S_STOPPED) return LOUVAIN_ESTATE;
+    CK(hipMemcpyAsync(labels, ctx->Cp, sizeof(int32_t) * (size_t)ctx->lev.n,
+                      hipMemcpyDeviceToDevice, ctx->s));
+    TRY(sync_stream(ctx));
+    return LOUVAIN_OK;
+}
+
+int louvain_level_graph(louvain_ctx *ctx, const int32_t **offsets, const int32_t **degree,
+                        const int32_t **targets, const void **weights, int32_t *n_level,
+                        int32_t *weight_bytes)
+{
+    if (!ctx) return LOUVAIN_EINVAL;
+    if (offsets) *offsets = ctx->lev.off;
+    if (degree) *degree = ctx->lev.deg;
+    if (targets) *targets = ctx->lev.tgt;
+    if (weights) *weights = ctx->lev.w;
+    if (n_level) *n_level = ctx->lev.n;
+    if (weight_bytes) *weight_bytes = ctx->lev.wbytes;
+    return LOUVAIN_OK;
+}
+
+int louvain_move_trace(louvain_ctx *ctx, int32_t max, int64_t *sumN_hi, uint64_t *sumN_lo,
+                       int64_t *moves, int64_t *processed, int32_t *count)
+{
+    if (!ctx || max < 0) return LOUVAIN_EINVAL;
+    const int32_t k = std::min<int32_t>(max, (int32_t)ctx->tr_sum.size());
+    for (int32_t i = 0; i < k; ++i) {
+        if (sumN_hi) sumN_hi[i] = (int64_t)(ctx->tr_sum[i] >> 64);
+        if (sumN_lo) sumN_lo[i] = (uint64_t)ctx->tr_sum[i];
+        if (moves) moves[i] = ctx->tr_moves[i];
+        if (processed) processed[i] = ctx->tr_proc[i];
+    }
+    if (count) *count = (int32_t)ctx->tr_sum.size();
+    return LOUVAIN_OK;
+}
+
+int louvain_reset(louvain_ctx *ctx)
+{
+    if (!ctx) return LOUVAIN_EINVAL;
+    reset_state(ctx);
+    launch_iota(ctx->top, ctx->n, ctx->s);
+    CKL();
+    TRY(sync_stream(ctx));
+    return LOUVAIN_OK;
+}
+
+int louvain_total_weight(louvain_ctx *ctx, int64_t *W)
+{
+    if (!ctx || !W) return LOUVAIN_EINVAL;
+    *W = ctx->W;
+    return LOUVAIN_OK;
+}
+
+int louvain_get_stats(louvain_ctx *ctx, louvain_stats *stats)
+{
+    if (!ctx || !stats) return LOUVAIN_EINVAL;
+    *stats = ctx->st;
+    return LOUVAIN_OK;
+}
+
+int louvain_kernel_stats(louvain_ctx *ctx, louvain_kernel_stat *out, int32_t max, int32_t *count)
+{
+    if (!ctx || max < 0 || (max > 0 && !out)) return LOUVAIN_EINVAL;
+    // algorithmic bytes from the work counters (whole context lifetime)
+    if (hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->s) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->s) != hipSuccess)
+        return LOUVAIN_EHIP;
+    const double sb = ctx->L.sb;
+    const double wb_in = 4.0;
+    int32_t k = 0;
+    for (int f = 0; f < F_COUNT; ++f) {
+        double bytes = 0.0;
+        if (f >= F_MOVE0 && f < F_MOVE0 + NBINS) {
+            const unsigned long long *w = ctx->hsc->work[WORK_MOVE + f - F_MOVE0];
+            // per vertex: row offsets 8, K' sb, C' 4, active flag 1; per entry: target 4,
+            // weight, C'[j] 4; per distinct community: Sigma' sb; per move: C' 4, two
+            // Sigma' updates 2*sb, two size updates 8
+            bytes = (double)w[0] * (8 + sb + 4 + 1) + (double)w[1] * (4 + wb_in + 4) +
+                    (double)w[2] * sb + (double)w[3] * (4 + 2 * sb + 8);
+        } else if (f >= F_AGG0 && f < F_AGG0 + NBINS) {
+            const unsigned long long *w = ctx->hsc->work[WORK_AGG + f - F_AGG0];
+            // per community: member offsets 8, row offset 8, row length 4; per member: id 4,
+            // its row offsets 8; per entry: target 4, weight, C'[j] 4; per emitted entry:
+            // target 4 and weight sb
+            bytes = (double)w[0] * 20 + (double)w[1] * 12 + (double)w[2] * (4 + wb_in + 4) +
+                    (double)w[3] * (4 + sb);
+        }
+        ctx->fam_bytes[f] = bytes;
+        if (k < max) {
+            memset(&out[k], 0, sizeof(out[k]));
+            strncpy(out[k].name, FAM_NAMES[f], sizeof(out[k].name) - 1);
+            out[k].launches = ctx->fam_launches[f];
+            out[k].ms = ctx->fam_ms[f];
+            out[k].bytes = bytes;
+        }
+        ++k;
+    }
+    if (count) *count = k;
+    return LOUVAIN_OK;
+}
+
+void louvain_destroy(louvain_ctx *ctx)
+{
+    if (!ctx) return;
+    for (const Pending &q : ctx->pending) {
+        hipEventDestroy(q.a);
+        hipEventDestroy(q.b);
+    }
+    for (hipEvent_t e : ctx->ev_free) hipEventDestroy(e);
+    if (ctx->hsc) hipHostFree(ctx->hsc);
+    if (ctx->pinned_done) hipHostFree(ctx->pinned_done);
+    for (int k = 0; k < 2; ++k)
+        if (ctx->it_ev[k]) hipEventDestroy(ctx->it_ev[k]);
+    delete ctx;
+}
+
+const char *louvain_strerror(int code)
+{
+    switch (code) {
+    case LOUVAIN_OK: return "ok";
+    case LOUVAIN_EINVAL: return "invalid argument or malformed graph";
+    case LOUVAIN_EOVERFLOW: return "size or total weight out of range";
+    case LOUVAIN_ENOSPC: return "workspace too small";
+    case LOUVAIN_EHIP: return g_last_hip_error;
+    case LOUVAIN_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

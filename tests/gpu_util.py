@@ -1,0 +1,45 @@
+"""Helpers of the GPU parity tests: upload CSR graphs, canonical forms of level graphs."""
+import numpy as np
+
+import oracle
+
+
+def to_device(csr):
+    import torch
+    off = torch.from_numpy(csr.offsets32()).cuda()
+    tgt = torch.from_numpy(np.ascontiguousarray(csr.targets, dtype=np.int32)).cuda()
+    w = torch.from_numpy(np.ascontiguousarray(csr.weights, dtype=np.int32)).cuda()
+    return off, tgt, w
+
+
+def canonical(offsets, degree, targets, weights):
+    """A holey GPU level graph as an oracle Graph: rows sorted by target, gaps removed."""
+    off = offsets.cpu().numpy().astype(np.int64)
+    n = len(off) - 1
+    deg = degree.cpu().numpy().astype(np.int64) if degree is not None else np.diff(off)
+    tgt = targets.cpu().numpy()
+    w = weights.cpu().numpy().astype(np.int64)
+    new_off = np.zeros(n + 1, dtype=np.int64)
+    new_off[1:] = np.cumsum(deg)
+    out_t = np.empty(int(new_off[n]), dtype=np.int32)
+    out_w = np.empty(int(new_off[n]), dtype=np.int64)
+    for i in range(n):
+        a, d = int(off[i]), int(deg[i])
+        r_t = tgt[a:a + d]
+        order = np.argsort(r_t, kind="stable")
+        out_t[new_off[i]:new_off[i + 1]] = r_t[order]
+        out_w[new_off[i]:new_off[i + 1]] = w[a:a + d][order]
+    return oracle.Graph(n, new_off, out_t, out_w)
+
+
+def same_graph(a, b) -> bool:
+    return (a.n == b.n and np.array_equal(a.offsets, b.offsets)
+            and np.array_equal(a.targets, b.targets) and np.array_equal(a.weights, b.weights))
+
+
+def is_valid_partition(memb: np.ndarray) -> bool:
+    """Dense labels 0..k-1, each used, assigned in order of first use of the old labels."""
+    if memb.size == 0:
+        return True
+    k = int(memb.max()) + 1
+    return memb.min() == 0 and np.unique(memb).size == k

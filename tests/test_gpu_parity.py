@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path through its C ABI against the oracle.
+
+Deterministic mode: bit-exact against the oracle's synchronous mode after every
+pass (iterations, exact per-iteration gain sums, moves, raw labels, community
+counts, canonical super-vertex graph), then the final membership and Q.
+Fast mode: a valid partition whose reported Q equals the oracle's Q of the
+same membership bit for bit, within 0.01 of the oracle's sequential Q, and an
+aggregation that is bit-exact for its own membership.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from gpu_util import canonical, is_valid_partition, same_graph, to_device
+from refs import random_graph
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "reference.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2312_04876_amd as P
+    P.load_library()
+
+
+def _og(csr):
+    return oracle.as_graph(csr.offsets, csr.targets, csr.weights)
+
+
+def _isolated(g):
+    return int((np.diff(g.offsets) == 0).sum())
+
+
+def det_parity(csr, round_bits=1, seed=0, max_passes=10, max_iterations=20, prune=True,
+               tolerance=0.01):
+    """Step the GPU deterministic mode pass by pass against the oracle's sync mode."""
+    import paper_2312_04876_amd as P
+    print("det parity:", csr.name or "graph", csr.n, csr.nnz, "round_bits", round_bits,
+          "seed", seed, flush=True)
+    g = _og(csr)
+    prm = oracle.Params(mode="sync", seed=seed, sample_bits=round_bits, max_passes=max_passes,
+                        max_iterations=max_iterations, prune=prune, tolerance=tolerance)
+    memb_o, q_o, recs = oracle.louvain_trace(g, prm)
+    off, tgt, w = to_device(csr)
+    ctx = P.Louvain(off, tgt, w, mode="deterministic", seed=seed, round_bits=round_bits,
+                    max_passes=max_passes, max_iterations=max_iterations, prune=prune,
+                    tolerance=tolerance)
+    try:
+        for k, rec in enumerate(recs):
+            it, _dq = ctx.move()
+            assert it == rec.trace.iterations, ("iterations", k)
+            tr = ctx.move_trace()
+            assert tr["sumN"] == rec.trace.sumN, ("gain sums", k)
+            assert tr["moves"] == rec.trace.moves, ("moves", k)
+            iso = _isolated(rec.level)
+            # isolated vertices are never queued on the GPU; the oracle visits them in the
+            # first iteration (with pruning) or in every iteration (without)
+            exp_proc = [p - (iso if (k2 == 0 or not prune) else 0)
+                        for k2, p in enumerate(rec.trace.processed)]
+            assert tr["processed"] == exp_proc, ("processed", k)
+            labels = ctx.level_labels().cpu().numpy()
+            assert np.array_equal(labels, rec.raw_labels), ("labels", k)
+            nc, stop = ctx.aggregate()
+            assert nc == rec.communities, ("communities", k)
+            if rec.next_level is None:
+                assert stop
+                break
+            assert same_graph(canonical(*ctx.level_graph()), rec.next_level), ("level graph", k)
+            assert stop == (k + 1 == max_passes)
+        memb, q, st = ctx.run()
+        memb = memb.cpu().numpy()
+        assert np.array_equal(memb, memb_o)
+        assert q == q_o
+        assert st["iterations"] == [r.trace.iterations for r in recs]
+    finally:
+        ctx.close()
+
+
+# ----------------------------------------------------------------- deterministic mode
+
+def small_graphs():
+    yield graphgen.from_edges(4, [(0, 1), (1, 2), (2, 3)], name="path4")
+    yield graphgen.cliques(6, 5, name="cliques6x5")
+    yield graphgen.cliques(3, 4, bridges=[(3, 4), (7, 8)], name="bridged")
+    rng = np.random.default_rng(5)
+    for n in (12, 40, 90):
+        e, w = random_graph(rng, n, 0.2, wmax=7, self_loops=True)
+        yield graphgen.from_edges(n, e, w, name="rand%d" % n)
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_det_small(idx):
+    det_parity(list(small_graphs())[idx])
+
+
+@pytest.mark.parametrize("wl", ["sbm10k", "rmat12-8", "rmat14-16", "rmat16-16"])
+def test_det_workloads(wl):
+    det_parity(graphgen.workload(wl))
+
+
+@pytest.mark.parametrize("round_bits,seed", [(0, 0), (2, 7), (3, 11)])
+def test_det_round_settings(round_bits, seed):
+    det_parity(graphgen.workload("rmat13-8"), round_bits=round_bits, seed=seed)
+
+
+def test_det_weighted_and_no_prune():
+    det_parity(graphgen.rmat(13, 12, wmax=8, seed=9, name="rmat13w"), prune=False)
+    det_parity(graphgen.workload("sbm10k"), max_passes=2, max_iterations=5, tolerance=0.0)
+
+
+def hub_graph():
+    """An R-MAT background plus a star whose centre has 10,000 neighbours (HBM-table bin)
+    and a dense block, so every degree bin is exercised in moving and aggregation."""
+    base = graphgen.rmat(14, 8, seed=21)
+    src = np.repeat(np.arange(base.n), np.diff(base.offsets))
+    edges = [(int(a), int(b)) for a, b in zip(src, base.targets) if a < b]
+    n = base.n
+    edges += [(0, v) for v in range(1, 10001)]
+    edges += [(i, j) for i in range(10100, 10220) for j in range(i + 1, 10220)]
+    return graphgen.from_edges(n, edges, name="hub")
+
+
+def test_det_hub_bins():
+    det_parity(hub_graph())
+
+
+def test_det_edge_cases():
+    for csr in [graphgen.from_edges(0, [], name="empty"), graphgen.from_edges(1, [], name="one"),
+                graphgen.from_edges(7, [], name="isolated"),
+                graphgen.from_edges(3, [(1, 1)], [5], name="selfloop"),
+                graphgen.from_edges(2, [(0, 1)], [3], name="edge")]:
+        det_parity(csr)
+    det_parity(graphgen.workload("sbm10k"), max_passes=0)
+    det_parity(graphgen.workload("sbm10k"), max_passes=1)
+
+
+def test_det_repeatable_and_reset():
+    import paper_2312_04876_amd as P
+    csr = graphgen.workload("rmat14-16")
+    off, tgt, w = to_device(csr)
+    ctx = P.Louvain(off, tgt, w, mode="deterministic")
+    m1, q1, _ = ctx.run()
+    m1 = m1.cpu().numpy().copy()
+    ctx.reset()
+    m2, q2, _ = ctx.run()
+    assert np.array_equal(m1, m2.cpu().numpy()) and q1 == q2
+    ctx.close()
+
+
+# ----------------------------------------------------------------- fast mode
+
+def _golden():
+    return json.load(open(GOLDEN))
+
+
+def _fast_q(wl):
+    import paper_2312_04876_amd as P
+    csr = graphgen.workload(wl)
+    g = _og(csr)
+    off, tgt, w = to_device(csr)
+    memb, q, st = P.louvain(off, tgt, w, mode="fast")
+    memb = memb.cpu().numpy()
+    print(wl, "fast Q", q, "oracle seq Q", _golden()[wl]["seq"]["Q"], st, flush=True)
+    assert is_valid_partition(memb)
+    assert q == oracle.modularity(g, memb)
+    return q
+
+
+@pytest.mark.parametrize("wl", ["rmat16-16", "rmat18-16"])
+def test_fast_quality(wl):
+    # the R-MAT workloads run in fast mode: |Q - Q_oracle_seq| <= 0.01
+    assert abs(_fast_q(wl) - _golden()[wl]["seq"]["Q"]) <= 0.01
+
+
+def test_fast_quality_sbm():
+    # SBM-10k is a deterministic-mode workload; in fast mode it must not fall more than
+    # 0.01 below the sequential oracle (it lands above it: the oracle's own Q varies by
+    # about 0.012 over vertex orders on this graph, see the golden relabelling runs)
+    assert _fast_q("sbm10k") >= _golden()["sbm10k"]["seq"]["Q"] - 0.01
+
+
+@pytest.mark.parametrize("wl", ["rmat14-16", "sbm10k"])
+def test_fast_aggregation_exact_for_own_membership(wl):
+    import paper_2312_04876_amd as P
+    csr = graphgen.workload(wl)
+    g = _og(csr)
+    off, tgt, w = to_device(csr)
+    ctx = P.Louvain(off, tgt, w, mode="fast")
+    level = g
+    for _ in range(4):
+        ctx.move()
+        labels = ctx.level_labels().cpu().numpy()
+        nc, stop = ctx.aggregate()
+        dense, nco = oracle.renumber(labels)
+        assert nc == nco
+        if stop:
+            break
+        nxt = oracle.aggregate(level, dense, nc)
+        assert same_graph(canonical(*ctx.level_graph()), nxt)
+        # the singletons of the new level keep the modularity of the membership
+        assert oracle.modularity_exact(nxt, np.arange(nc, dtype=np.int32)) == \
+            oracle.modularity_exact(level, dense)
+        level = nxt
+    ctx.close()
+
+
+def test_fast_hub_graph():
+    import paper_2312_04876_amd as P
+    csr = hub_graph()
+    g = _og(csr)
+    off, tgt, w = to_device(csr)
+    memb, q, _ = P.louvain(off, tgt, w, mode="fast")
+    memb = memb.cpu().numpy()
+    assert is_valid_partition(memb)
+    assert q == oracle.modularity(g, memb)
+    _, q_seq, _ = oracle.louvain(g, oracle.Params(mode="seq"))
+    assert abs(q - q_seq) <= 0.01
+
+
+# ----------------------------------------------------------------- full size (R-MAT scale 22)
+
+@pytest.fixture(scope="module")
+def rmat22():
+    return graphgen.workload("rmat22")
+
+
+def test_rmat22_fast_full_size(rmat22):
+    import paper_2312_04876_amd as P
+    print("rmat22 fast mode", rmat22.n, rmat22.nnz, flush=True)
+    g = _og(rmat22)
+    off, tgt, w = to_device(rmat22)
+    memb, q, st = P.louvain(off, tgt, w, mode="fast")
+    memb = memb.cpu().numpy()
+    print("rmat22 fast Q", q, st, flush=True)
+    assert is_valid_partition(memb)
+    assert q == oracle.modularity(g, memb)
+    assert abs(q - _golden()["rmat22"]["seq"]["Q"]) <= 0.01
+
+
+def test_rmat22_det_full_size(rmat22):
+    import paper_2312_04876_amd as P
+    print("rmat22 deterministic mode", flush=True)
+    off, tgt, w = to_device(rmat22)
+    memb, q, st = P.louvain(off, tgt, w, mode="deterministic", seed=0, round_bits=1)
+    memb = memb.cpu().numpy()
+    ref = _golden()["rmat22"]["sync"]
+    assert st["iterations"] == ref["iterations"]
+    assert st["communities"] == ref["communities"]
+    assert hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest() == ref["digest"]
+    assert q == ref["Q"]
