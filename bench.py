@@ -42,8 +42,9 @@ def parse():
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--mode", default="fast", choices=["fast", "deterministic"])
     ap.add_argument("--round-bits", type=int, default=1)
-    ap.add_argument("--cpu-baseline", default="rmat20-16",
-                    help="workload the oracle is timed on ('none' to skip)")
+    ap.add_argument("--cpu-baseline", default="same",
+                    help="workload the oracle is timed on: 'same' (the benchmark workload, "
+                         "one whole run), a workload name, or 'none'")
     ap.add_argument("--no-profile", action="store_true")
     return ap.parse_args()
 
@@ -148,7 +149,7 @@ def main():
 
     cpu = None
     if args.cpu_baseline != "none":
-        cpu = cpu_baseline(args.cpu_baseline)
+        cpu = cpu_baseline(args.workload if args.cpu_baseline == "same" else args.cpu_baseline)
         print("cpu baseline: %s" % cpu["sample"], file=sys.stderr, flush=True)
 
     line = {
