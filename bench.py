@@ -46,7 +46,114 @@ def parse():
                     help="workload the oracle is timed on: 'same' (the benchmark workload, "
                          "one whole run), a workload name, or 'none'")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 3 plain device copies of MIB MiB (calibrates the HBM byte "
+                         "counters of a profiler against a kernel of known traffic) and exit")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="summarise four rocprofv3 --pmc output directories (FETCH_SIZE and "
+                         "WRITE_SIZE of one bench step, then of the copy probe) into --pmc-out")
+    ap.add_argument("--pmc-out", default=os.path.join(ROOT, "profiles", "rmat22_fast_pmc.json"))
     return ap.parse_args()
+
+
+# Kernel family (as named by louvain_kernel_stats) -> the device kernels of one launch.
+FAMILY_KERNELS = {
+    "move_bin0_2lanes": [r"k_move_wave<[^>]*>, 2, 4, 4,"],
+    "move_bin1_8lanes": [r"k_move_wave<[^>]*>, 8, 4, 6,"],
+    "move_bin2_32lanes": [r"k_move_wave<[^>]*>, 32, 4, 8,"],
+    "move_bin3_wave": [r"k_move_wave<[^>]*>, 64, 8, 10,"],
+    "move_bin4_block": [r"k_move_block<[^>]*>, 256,"],
+    "move_bin5_bigblock": [r"k_move_block<[^>]*>, 512,"],
+    "move_bin6_hub": [r"k_move_hub<", r"k_move_hub_scatter<"],
+    "agg_bin6_hub": [r"k_agg_hub_scatter<", r"k_agg_hub_emit<"],
+}
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2312_04876_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "louvain.h"), "rb").read())
+    return h.hexdigest()
+
+
+def _pmc_rows(d):
+    import csv
+    import glob
+    rows = []
+    for p in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        rows += list(csv.DictReader(open(p)))
+    return rows
+
+
+def pmc_summary(dirs, out):
+    """Per-kernel HBM traffic per dispatch from FETCH_SIZE / WRITE_SIZE runs, scaled by what the
+    same counters read for the copy probe (bytes actually moved / counter bytes)."""
+    import re
+    fetch, write, cfetch, cwrite = (_pmc_rows(d) for d in dirs)
+
+    def per_kernel(rows, counter):
+        acc = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            k = acc.setdefault(r["Kernel_Name"], [0, 0.0])
+            k[0] += 1
+            k[1] += float(r["Counter_Value"]) * 1024.0  # KiB per dispatch
+        return acc
+
+    def copy_factor(rows, counter):
+        got = sum(v[1] for k, v in per_kernel(rows, counter).items() if "copyBuffer" in k)
+        return (3 * 1024 * (1 << 20)) / got  # the probe copies 1 GiB three times
+
+    ff, wf = copy_factor(cfetch, "FETCH_SIZE"), copy_factor(cwrite, "WRITE_SIZE")
+    f, w = per_kernel(fetch, "FETCH_SIZE"), per_kernel(write, "WRITE_SIZE")
+    kernels = {}
+    for name in f:
+        kernels[name] = {"dispatches": f[name][0], "fetch_bytes": f[name][1] * ff,
+                         "write_bytes": w.get(name, [0, 0.0])[1] * wf}
+    fam = {}
+    for family, pats in FAMILY_KERNELS.items():
+        ks = [k for k in kernels if any(re.search(p, k) for p in pats)]
+        if not ks:
+            continue
+        main = [k for k in ks if re.search(pats[0], k)]
+        launches = sum(kernels[k]["dispatches"] for k in main)
+        total = sum(kernels[k]["fetch_bytes"] + kernels[k]["write_bytes"] for k in ks)
+        fam[family] = {"launches": launches, "bytes_per_launch": total / max(launches, 1)}
+    data = {"sources_sha256": sources_digest(), "fetch_factor": ff, "write_factor": wf,
+            "families": fam, "kernels": kernels}
+    with open(out, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    print(json.dumps({"fetch_factor": ff, "write_factor": wf, "families": fam}, indent=1))
+
+
+def measured_traffic(family, path):
+    """HBM bytes per launch of `family` from the PMC summary, if it was taken on these sources."""
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    if data.get("sources_sha256") != sources_digest():
+        return None
+    f = data.get("families", {}).get(family)
+    return f["bytes_per_launch"] if f else None
+
+
+def copy_probe(mib):
+    """Three device-to-device copies of a known size: reads and writes mib MiB each."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "copies": 3}))
 
 
 def run_steps(ctx, memb, steps):
@@ -78,6 +185,12 @@ def cpu_baseline(name):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.pmc_out)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the Louvain path here runs on a single MI355X "
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
@@ -129,8 +242,11 @@ def main():
         hot = [k for k in kernels if k["name"].startswith(("move_", "agg_"))]
         dom = max(hot, key=lambda k: k["ms_per_step"])
         gbs = dom["bytes_per_step"] / (dom["ms_per_step"] * 1e-3) / 1e9 if dom["ms_per_step"] else 0.0
+        traffic = measured_traffic(dom["name"], args.pmc_out) if args.workload == "rmat22" else None
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom["name"],
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["name"],
+                    "algorithmic_bytes_per_launch": dom["bytes_per_step"] * args.steps /
+                    max(dom["launches"], 1),
                     "launches_per_step": dom["launches"] / args.steps,
                     "ms_per_step": round(dom["ms_per_step"], 4),
                     "algorithmic_bytes_per_step": dom["bytes_per_step"]}

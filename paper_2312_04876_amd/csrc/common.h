@@ -32,29 +32,53 @@ typedef Cfg<int64_t, int64_t, i128> CfgWide;       // W >= 2^31, aggregated leve
 // ---------------------------------------------------------------------------
 // Degree bins.  A vertex (or, in aggregation, a community with its total
 // member degree) goes to the bin of its row length d:
-//   bin 0: d in [1, 8]      8 lanes per row, 16-slot LDS table
-//   bin 1: d in [9, 32]     32 lanes, 64 slots
-//   bin 2: d in [33, 128]   one wavefront, 256 slots
-//   bin 3: d in [129, 512]  one wavefront, 1024 slots
-//   bin 4: d in [513, 4096] one 256-thread workgroup, up to 8192 LDS slots
-//   bin 5: d > 4096         one 256-thread workgroup, table in HBM
+//   bin 0: d in [1, 8]        2 lanes per row (4 entries each), 16-slot LDS table
+//   bin 1: d in [9, 32]       8 lanes (4 entries each), 64 slots
+//   bin 2: d in [33, 128]     32 lanes (4 entries each), 256 slots
+//   bin 3: d in [129, 512]    one wavefront (8 entries per lane), 1024 slots
+//   bin 4: d in [513, 2048]   one 256-thread workgroup, up to 4096 LDS slots
+//   bin 5: d in [2049, L]     one 512-thread workgroup, LDS table of up to 2L slots
+//   bin 6: d > L              hubs: row slices + table in HBM
+// L (the LDS row limit) is 8192 with 4-byte table values and 4096 with 8-byte
+// ones, so the bin-5 table fits the 160 KB of LDS a gfx950 workgroup may use.
 // Every table has at least twice as many slots as the row has entries, so
 // linear probing always finds a free slot.
-constexpr int NBINS = 6;
-constexpr int BIN_HI[NBINS] = {8, 32, 128, 512, 4096, 0x7fffffff};
-constexpr int LDS_MAX_DEG = 4096;
-constexpr int BLOCK_LOG2S_MAX = 13;  // 8192 slots
+constexpr int NBINS = 7;
+constexpr int LDS_MAX_NARROW = 8192;
+constexpr int LDS_MAX_WIDE = 4096;
 constexpr int HUB_THREADS = 256;
+constexpr int BLOCK_THREADS = 512;
+// Hub rows (and hub communities in aggregation) are cut into slices of
+// HUB_SLICE entries; one workgroup folds a slice into an LDS table of
+// 2^HUB_LOG2S slots and then merges it into the row's HBM table, so repeated
+// communities are combined in LDS before they reach HBM atomics.
+constexpr int HUB_SLICE = 2048;
+constexpr int HUB_LOG2S = 12;
+// Rows per workgroup of the binning and compaction kernels.
+constexpr int BIN_CHUNK = 4096;
+// Vertices per workgroup (and LDS table slots / 2) of the community counting kernels.
+constexpr int COMM_CHUNK = 2048;
+constexpr int COMM_LOG2S = 12;
 
-__host__ __device__ inline int bin_of(int64_t d)
+__host__ __device__ inline int bin_of(int64_t d, int lds_max)
 {
     if (d <= 0) return -1;
     if (d <= 8) return 0;
     if (d <= 32) return 1;
     if (d <= 128) return 2;
     if (d <= 512) return 3;
-    if (d <= LDS_MAX_DEG) return 4;
-    return 5;
+    if (d <= 2048) return 4;
+    if (d <= lds_max) return 5;
+    return 6;
+}
+
+// log2 of the LDS table of a bin-4 row of length d: the smallest power of two
+// >= 2d, at least 64 slots.
+__host__ __device__ inline int block_log2s(int d)
+{
+    int l = 6;
+    while ((1 << l) < 2 * d) ++l;
+    return l;
 }
 
 // HBM table size for a hub row of length d (a multiple of 64, >= 2d).
@@ -71,14 +95,16 @@ struct DevScalars {
     int32_t done;
     int32_t iters;
     int32_t bin_count[8];   // active vertices per bin in the current round
-    int32_t bin_cursor[8];  // fill cursors of the binning step
-    int32_t bin_total[8];   // vertices per bin (binning step)
+    int32_t bin_start[8];   // bin boundaries of the binning step (NBINS + 1 used)
+    int32_t bin_maxlen[8];  // longest row per bin (binning step)
     int32_t mv_count;       // deferred moves of the current round (deterministic mode)
     int32_t pad0;
     // --- fields above are cleared at the start of every local-moving phase ---
     int32_t err;            // validation: bit 0 offsets, 1 targets, 2 weights
     int32_t pad1;
     unsigned long long scan_total;
+    unsigned long long hub_slices;   // row slices of the hub bin (sum over hubs)
+    unsigned long long hub_tslices;  // table slices of the hub bin (aggregation)
     unsigned long long W;
     unsigned long long sigma;       // sum of intra-community entries
     unsigned long long s2[2];       // 128-bit sum of Sigma_c^2
@@ -86,11 +112,11 @@ struct DevScalars {
     int32_t pad[16];
 };
 
-// Work-counter slots (DevScalars::work[k]): move bins 0..5
-// [vertices, entries, new keys, moves, -], aggregation bins 6..11
-// [communities, members, entries, emitted, -].
+// Work-counter slots (DevScalars::work[k]): move bins 0..NBINS-1
+// [vertices, entries, distinct communities, moves, -], aggregation bins
+// NBINS..2*NBINS-1 [communities, members, entries, emitted, -].
 constexpr int WORK_MOVE = 0;
-constexpr int WORK_AGG = 6;
+constexpr int WORK_AGG = NBINS;
 
 // ---------------------------------------------------------------------------
 // Device helpers.
@@ -156,6 +182,21 @@ __host__ __device__ inline int round_of(uint64_t seed, int round_bits, int pass,
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     return (int)(z >> (64 - round_bits));
+}
+
+// Index h with start[h] <= k < start[h + 1] in a non-decreasing start[0..n]
+// (the last such h when several starts are equal).
+__device__ inline int owner_slice(const int32_t *start, int n, int k)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= k)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 // Row of vertex v: [off[v], off[v] + length) with length from the degree

@@ -192,24 +192,23 @@ __device__ inline int block_scan_int(int x, int *wsum, int *tot)
     return wb + inc;  // inclusive
 }
 
-// Bins 4 and 5: one workgroup per community; the table is in LDS (bin 4,
-// 2^log2s slots) or in HBM (bin 5, hub_slots(min(total degree, |Gamma|))).
-template <class C, bool HBM>
-__global__ __launch_bounds__(256) void k_agg_block(AggArgs<C> a, int32_t ncomm)
+// Bins 4-5: one workgroup per community with an LDS table (dynamic shared
+// memory of 2^log2s_max slots) of block_log2s(total member degree) slots.
+template <class C>
+__global__ __launch_bounds__(256) void k_agg_block(AggArgs<C> a, int log2s_max)
 {
     typedef typename C::ST ST;
-    constexpr int S = HBM ? 1 : (1 << BLOCK_LOG2S_MAX);
-    __shared__ ST s_vals[S];
-    __shared__ int32_t s_keys[S];
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int S = 1 << log2s_max;
+    ST *s_vals = (ST *)smem;
+    int32_t *s_keys = (int32_t *)(smem + (size_t)S * sizeof(ST));
     __shared__ int32_t s_incl[256];
     __shared__ int32_t s_rb[256];
     __shared__ int32_t wsum[4];
     __shared__ int32_t s_cnt;
-    if (!HBM) {
-        for (int s = threadIdx.x; s < S; s += 256) {
-            s_keys[s] = -1;
-            s_vals[s] = 0;
-        }
+    for (int s = threadIdx.x; s < S; s += 256) {
+        s_keys[s] = -1;
+        s_vals[s] = 0;
     }
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
@@ -217,24 +216,7 @@ __global__ __launch_bounds__(256) void k_agg_block(AggArgs<C> a, int32_t ncomm)
     for (int idx = blockIdx.x; idx < a.count; idx += gridDim.x) {
         const int c = a.cbinorder[a.begin + idx];
         const int mb = a.coff[c], me = a.coff[c + 1];
-        int32_t *keys;
-        ST *vals;
-        uint32_t T = 0;
-        int log2s = 0;
-        if (HBM) {
-            const int64_t t0 = a.hoff[idx];
-            int64_t cap = (int64_t)(a.yoff[c + 1] - a.yoff[c]);
-            if (cap > ncomm) cap = ncomm;
-            T = (uint32_t)hub_slots(cap);
-            keys = a.hkeys + t0;
-            vals = a.hvals + t0;
-        } else {
-            const int tot = a.yoff[c + 1] - a.yoff[c];
-            log2s = 32 - __clz(2 * tot - 1);
-            if (log2s < 6) log2s = 6;
-            keys = s_keys;
-            vals = s_vals;
-        }
+        const int log2s = block_log2s(a.yoff[c + 1] - a.yoff[c]);
         for (int m0 = mb; m0 < me; m0 += 256) {
             const int mi = m0 + threadIdx.x;
             int rl = 0, rb = 0;
@@ -252,34 +234,20 @@ __global__ __launch_bounds__(256) void k_agg_block(AggArgs<C> a, int32_t ncomm)
             for (int t = threadIdx.x; t < total; t += 256) {
                 const int L = owner_of(s_incl, 256, t);
                 const int e = s_rb[L] + (t - (L ? s_incl[L - 1] : 0));
-                const int k = a.Cp[a.tgt[e]];
-                if (HBM)
-                    hbm_add<ST>(keys, vals, T, k, (ST)a.w[e]);
-                else
-                    lds_add<ST>(keys, vals, log2s, k, (ST)a.w[e]);
+                lds_add<ST>(s_keys, s_vals, log2s, a.Cp[a.tgt[e]], (ST)a.w[e]);
                 ++ne_;
             }
             __syncthreads();
         }
-        if (HBM) __threadfence();
         const int ybeg = a.yoff[c];
-        const uint32_t n_slots = HBM ? T : (1u << log2s);
-        for (uint32_t s = threadIdx.x; s < n_slots; s += 256) {
-            int k;
-            ST x;
-            if (HBM) {
-                k = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                x = k >= 0 ? __hip_atomic_load(&vals[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-            } else {
-                k = keys[s];
-                x = k >= 0 ? vals[s] : 0;
-            }
+        for (int s = threadIdx.x; s < (1 << log2s); s += 256) {
+            const int k = s_keys[s];
             if (k >= 0) {
                 const int pos = atomicAdd(&s_cnt, 1);
                 a.ytgt[ybeg + pos] = k;
-                a.yw[ybeg + pos] = x;
-                keys[s] = -1;
-                vals[s] = 0;
+                a.yw[ybeg + pos] = s_vals[s];
+                s_keys[s] = -1;
+                s_vals[s] = 0;
             }
         }
         __syncthreads();
@@ -289,7 +257,6 @@ __global__ __launch_bounds__(256) void k_agg_block(AggArgs<C> a, int32_t ncomm)
             s_cnt = 0;
             ++nc_;
         }
-        if (HBM) __threadfence();
         __syncthreads();
     }
     nc_ = wave_sum_u64(nc_);
@@ -304,6 +271,137 @@ __global__ __launch_bounds__(256) void k_agg_block(AggArgs<C> a, int32_t ncomm)
     }
 }
 
+// Bin 5 (hub communities), step 1: one workgroup per HUB_SLICE-entry window of
+// the concatenated member rows of a community (window w of community idx is
+// slice cslice[idx] + w); the window is folded into an LDS table and the table
+// is added into the community's HBM table of hub_slots(min(total, |Gamma|))
+// slots at hoff[idx].
+template <class C>
+__global__ __launch_bounds__(256) void k_agg_hub_scatter(AggArgs<C> a, int32_t nh)
+{
+    typedef typename C::ST ST;
+    constexpr int S = 1 << HUB_LOG2S;
+    __shared__ ST s_vals[S];
+    __shared__ int32_t s_keys[S];
+    __shared__ int32_t s_start[257];
+    __shared__ int32_t s_rb[256];
+    __shared__ int32_t s_m0;
+    const int k = (int)blockIdx.x;
+    const int idx = owner_slice(a.cslice, nh, k);
+    const int c = a.cbinorder[a.begin + idx];
+    const int mb = a.coff[c], me = a.coff[c + 1];
+    const int base = a.mpre[mb];
+    const int tot = a.mpre[me] - base;
+    const int w0 = (k - a.cslice[idx]) * HUB_SLICE;
+    const int w1 = min(w0 + HUB_SLICE, tot);
+    for (int s = threadIdx.x; s < S; s += 256) {
+        s_keys[s] = -1;
+        s_vals[s] = 0;
+    }
+    if (threadIdx.x == 0) {
+        // first member whose row ends after w0
+        int lo = mb, hi = me - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (a.mpre[mid + 1] - base > w0)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        s_m0 = lo;
+    }
+    __syncthreads();
+    unsigned long long ne_ = 0, nm_ = 0;
+    int m = s_m0;
+    for (;;) {
+        const int cnt = min(256, me - m);
+        if ((int)threadIdx.x < cnt) {
+            const int u = a.members[m + threadIdx.x];
+            s_rb[threadIdx.x] = a.off[u];
+            const int st = a.mpre[m + threadIdx.x] - base;
+            s_start[threadIdx.x] = st;
+            if (st >= w0 && st < w1 && a.mpre[m + threadIdx.x + 1] - base > st) ++nm_;
+        }
+        if (threadIdx.x == 0) s_start[cnt] = a.mpre[m + cnt] - base;
+        __syncthreads();
+        const int t_lo = max(w0, s_start[0]);
+        const int t_hi = min(w1, s_start[cnt]);
+        for (int t = t_lo + (int)threadIdx.x; t < t_hi; t += 256) {
+            const int L = owner_slice(s_start, cnt, t);
+            const int e = s_rb[L] + (t - s_start[L]);
+            lds_add<ST>(s_keys, s_vals, HUB_LOG2S, a.Cp[a.tgt[e]], (ST)a.w[e]);
+            ++ne_;
+        }
+        const bool more = s_start[cnt] < w1 && m + cnt < me;
+        __syncthreads();
+        if (!more) break;
+        m += cnt;
+    }
+    int64_t cap = tot;
+    if (cap > a.ncomm) cap = a.ncomm;
+    const uint32_t T = (uint32_t)hub_slots(cap);
+    const int64_t t0 = a.hoff[idx];
+    for (int s = threadIdx.x; s < S; s += 256) {
+        const int key = s_keys[s];
+        if (key >= 0) hbm_add<ST>(a.hkeys + t0, a.hvals + t0, T, key, s_vals[s]);
+    }
+    nm_ = wave_sum_u64(nm_);
+    ne_ = wave_sum_u64(ne_);
+    if ((threadIdx.x & 63) == 0) {
+        if (nm_) atomicAdd(&a.work[1], nm_);
+        if (ne_) atomicAdd(&a.work[2], ne_);
+    }
+}
+
+// Bin 5, step 2: one workgroup per HUB_SLICE slots of a community's HBM table
+// (slice tslice[idx] + j) appends the occupied slots to row c of the
+// super-vertex graph (position from an atomic on ydeg[c], zero on entry) and
+// clears them.
+template <class C>
+__global__ __launch_bounds__(256) void k_agg_hub_emit(AggArgs<C> a, int32_t nh)
+{
+    typedef typename C::ST ST;
+    __shared__ ST s_v[HUB_SLICE];
+    __shared__ int32_t s_k[HUB_SLICE];
+    __shared__ int32_t s_cnt, s_base;
+    const int k = (int)blockIdx.x;
+    const int idx = owner_slice(a.tslice, nh, k);
+    const int c = a.cbinorder[a.begin + idx];
+    int64_t cap = a.yoff[c + 1] - a.yoff[c];
+    if (cap > a.ncomm) cap = a.ncomm;
+    const uint32_t T = (uint32_t)hub_slots(cap);
+    const int64_t t0 = a.hoff[idx];
+    int32_t *keys = a.hkeys + t0;
+    ST *vals = a.hvals + t0;
+    const uint32_t s0 = (uint32_t)(k - a.tslice[idx]) * HUB_SLICE;
+    const uint32_t s1 = min(s0 + (uint32_t)HUB_SLICE, T);
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    for (uint32_t s = s0 + threadIdx.x; s < s1; s += 256) {
+        const int key = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (key >= 0) {
+            const ST x = __hip_atomic_load(&vals[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int pos = atomicAdd(&s_cnt, 1);
+            s_k[pos] = key;
+            s_v[pos] = x;
+            keys[s] = -1;
+            vals[s] = 0;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_base = s_cnt ? atomicAdd(&a.ydeg[c], s_cnt) : 0;
+        if (s_cnt) atomicAdd(&a.work[3], (unsigned long long)s_cnt);
+        if (s0 == 0) atomicAdd(&a.work[0], 1ull);
+    }
+    __syncthreads();
+    const int ybeg = a.yoff[c] + s_base;
+    for (int i = threadIdx.x; i < s_cnt; i += 256) {
+        a.ytgt[ybeg + i] = s_k[i];
+        a.yw[ybeg + i] = s_v[i];
+    }
+}
+
 inline int agg_grid(int count, int per_block)
 {
     int64_t g = ((int64_t)count + per_block - 1) / per_block;
@@ -315,7 +413,7 @@ inline int agg_grid(int count, int per_block)
 }  // namespace
 
 template <class C>
-void launch_aggregate(int bin, const AggArgs<C> &a, hipStream_t s)
+void launch_aggregate(int bin, const AggArgs<C> &a, int log2s_max, hipStream_t s)
 {
     if (a.count <= 0) return;
     switch (bin) {
@@ -323,23 +421,41 @@ void launch_aggregate(int bin, const AggArgs<C> &a, hipStream_t s)
     case 1: k_agg_wave<C, 32, 6><<<agg_grid(a.count, 8), 256, 0, s>>>(a); break;
     case 2: k_agg_wave<C, 64, 8><<<agg_grid(a.count, 4), 256, 0, s>>>(a); break;
     case 3: k_agg_wave<C, 64, 10><<<agg_grid(a.count, 4), 256, 0, s>>>(a); break;
-    case 4: k_agg_block<C, false><<<agg_grid(a.count, 1), 256, 0, s>>>(a, 0); break;
-    default: break;
+    case 4:
+    case 5: {
+        const size_t bytes = ((size_t)1 << log2s_max) * (sizeof(typename C::ST) + 4);
+        if (bytes > 65536) {
+            // raise the dynamic-LDS limit of this kernel to what the launch asks for;
+            // a failure shows up as a launch error at the caller's check
+            if (hipFuncSetAttribute((const void *)&k_agg_block<C>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+                hipSuccess)
+                (void)hipGetLastError();
+        }
+        k_agg_block<C><<<agg_grid(a.count, 1), 256, bytes, s>>>(a, log2s_max);
+        break;
+    }
+    default: break;  // hub communities: launch_aggregate_hub
     }
 }
 
 template <class C>
-void launch_aggregate_hub(const AggArgs<C> &a, int32_t ncomm, hipStream_t s)
+void launch_aggregate_hub(const AggArgs<C> &a, int32_t row_slices, int32_t table_slices,
+                          hipStream_t s)
 {
-    if (a.count <= 0) return;
-    k_agg_block<C, true><<<agg_grid(a.count, 1), 256, 0, s>>>(a, ncomm);
+    if (a.count <= 0 || row_slices <= 0) return;
+    k_agg_hub_scatter<C><<<row_slices, 256, 0, s>>>(a, a.count);
+    k_agg_hub_emit<C><<<table_slices, 256, 0, s>>>(a, a.count);
 }
 
-template void launch_aggregate<CfgNarrow>(int, const AggArgs<CfgNarrow> &, hipStream_t);
-template void launch_aggregate<CfgWideIn>(int, const AggArgs<CfgWideIn> &, hipStream_t);
-template void launch_aggregate<CfgWide>(int, const AggArgs<CfgWide> &, hipStream_t);
-template void launch_aggregate_hub<CfgNarrow>(const AggArgs<CfgNarrow> &, int32_t, hipStream_t);
-template void launch_aggregate_hub<CfgWideIn>(const AggArgs<CfgWideIn> &, int32_t, hipStream_t);
-template void launch_aggregate_hub<CfgWide>(const AggArgs<CfgWide> &, int32_t, hipStream_t);
+template void launch_aggregate<CfgNarrow>(int, const AggArgs<CfgNarrow> &, int, hipStream_t);
+template void launch_aggregate<CfgWideIn>(int, const AggArgs<CfgWideIn> &, int, hipStream_t);
+template void launch_aggregate<CfgWide>(int, const AggArgs<CfgWide> &, int, hipStream_t);
+template void launch_aggregate_hub<CfgNarrow>(const AggArgs<CfgNarrow> &, int32_t, int32_t,
+                                              hipStream_t);
+template void launch_aggregate_hub<CfgWideIn>(const AggArgs<CfgWideIn> &, int32_t, int32_t,
+                                              hipStream_t);
+template void launch_aggregate_hub<CfgWide>(const AggArgs<CfgWide> &, int32_t, int32_t,
+                                            hipStream_t);
 
 }  // namespace lv

@@ -4,9 +4,11 @@
 // over the table (Eq. 2 in exact integers, ties to the lowest community
 // id), and move / mark the row's vertices for the next iteration (pruning).
 //
-// Table placement by bin: groups of 8/32/64 lanes with private LDS tables
-// (bins 0-3), one workgroup with an LDS table of up to 8192 slots (bin 4),
-// one workgroup with an open-addressing table in HBM (bin 5, hubs).
+// Table placement by bin: groups of 2/8/32/64 lanes with private LDS tables
+// (bins 0-3), one workgroup with an LDS table (bins 4-5), row slices folded in
+// LDS and merged into an HBM table (hubs).  Every lane first loads its share
+// of the row (targets, weights, then the communities of the targets) into
+// registers so the independent loads are in flight together, then inserts.
 //
 // FAST = true applies each move at once (live C', Sigma', size; asynchronous
 // semantics); FAST = false records the move for the apply kernel so every
@@ -46,20 +48,20 @@ __device__ inline int lds_insert(int32_t *keys, ST *vals, int log2s, int32_t c, 
 // Insert into an HBM table of T slots (T >= 2 * row length); index by the
 // high half of hash * T.
 template <typename ST>
-__device__ inline int hbm_insert(int32_t *keys, ST *vals, uint32_t T, int32_t c, ST w)
+__device__ inline void hbm_insert(int32_t *keys, ST *vals, uint32_t T, int32_t c, ST w)
 {
     uint32_t h = (uint32_t)(((uint64_t)hash32((uint32_t)c) * (uint64_t)T) >> 32);
     for (;;) {
         const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (k == c) {
             atomic_add_t<ST>(&vals[h], w);
-            return 0;
+            return;
         }
         if (k < 0) {
             const int32_t old = atomicCAS(&keys[h], -1, c);
             if (old < 0 || old == c) {
                 atomic_add_t<ST>(&vals[h], w);
-                return old < 0 ? 1 : 0;
+                return;
             }
         }
         h = (h + 1 == T) ? 0u : h + 1;
@@ -77,7 +79,7 @@ __device__ inline bool better(SC s, int c, SC bs, int bc)
 // weight to the own community, non-self entries).  Returns true to move and
 // sets the gain N = best - stay.
 template <class C>
-__device__ inline bool decide(const MoveArgs<C> &a, int v, int dc, typename C::ST kv,
+__device__ inline bool decide(const MoveArgs<C> &a, int dc, typename C::ST kv,
                               typename C::SC best, int bc, typename C::ST hd, int nonself,
                               typename C::SC *gain)
 {
@@ -107,7 +109,7 @@ __device__ inline void commit(const MoveArgs<C> &a, int v, int dc, int bc, typen
     }
 }
 
-// Flush per-lane counters of a 256-thread block.
+// Flush per-lane counters (all lanes of every wavefront call this).
 template <class C>
 __device__ inline void flush_counters(const MoveArgs<C> &a, typename C::SC gain,
                                       unsigned long long nv, unsigned long long ne,
@@ -133,9 +135,29 @@ __device__ inline void flush_counters(const MoveArgs<C> &a, typename C::SC gain,
     }
 }
 
-// Bins 0-3: G lanes per vertex, 64/G vertices per wavefront, LDS table of
-// 2^LOG2S slots per group.
-template <class C, int G, int LOG2S, bool FAST>
+// Score of one table slot for vertex with label dc and weight kv; updates the
+// running best or the weight to the own community.
+template <class C>
+__device__ inline void consider(const MoveArgs<C> &a, int dc, typename C::ST kv, int k,
+                                typename C::ST x, typename C::ST sig, typename C::SC &best,
+                                int &bc, typename C::ST &hd)
+{
+    typedef typename C::SC SC;
+    if (k < 0) return;
+    if (k == dc) {
+        hd = x;
+        return;
+    }
+    const SC sc = (SC)a.W * (SC)x - (SC)kv * (SC)sig;
+    if (better(sc, k, best, bc)) {
+        best = sc;
+        bc = k;
+    }
+}
+
+// Bins 0-3: G lanes per vertex (64/G vertices per wavefront), each lane
+// holding up to E entries of the row, LDS table of 2^LOG2S slots per group.
+template <class C, int G, int E, int LOG2S, bool FAST>
 __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
 {
     typedef typename C::ST ST;
@@ -143,6 +165,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
     constexpr int S = 1 << LOG2S;
     constexpr int GPW = 64 / G;
     constexpr int NG = 4 * GPW;
+    constexpr int SPL = S / G;  // table slots scanned per lane
     __shared__ ST s_vals[NG * S];
     __shared__ int32_t s_keys[NG * S];
     if (*a.done) return;
@@ -152,9 +175,10 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
     const int grp = lane / G, gl = lane % G;
     int32_t *keys = s_keys + (wave * GPW + grp) * S;
     ST *vals = s_vals + (wave * GPW + grp) * S;
-    for (int s = gl; s < S; s += G) {
-        keys[s] = -1;
-        vals[s] = 0;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+        keys[gl + q * G] = -1;
+        vals[gl + q * G] = 0;
     }
     wave_sync();
     SC gain_acc = 0;
@@ -163,43 +187,53 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
     for (int base = (blockIdx.x * 4 + wave) * GPW; base < count; base += stride) {
         const int idx = base + grp;
         const bool has = idx < count;
-        int v = 0, beg = 0, d = 0;
+        const int v = has ? a.worklist[a.list_begin + idx] : 0;
+        int beg = 0, d = 0, dc = -1;
+        ST kv = 0;
         if (has) {
-            v = a.binorder[a.worklist[a.list_begin + idx]];
             beg = a.off[v];
             d = row_len(a.off, a.deg, v);
+            dc = a.Cp[v];
+            kv = a.K[v];
         }
+        int j[E], c[E];
+        ST w[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) j[k] = (gl + k * G < d) ? a.tgt[beg + gl + k * G] : -1;
+#pragma unroll
+        for (int k = 0; k < E; ++k) w[k] = (j[k] >= 0) ? (ST)a.w[beg + gl + k * G] : (ST)0;
+#pragma unroll
+        for (int k = 0; k < E; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
         int nonself = 0;
-        for (int e = gl; e < d; e += G) {
-            const int j = a.tgt[beg + e];
-            ++ne;
-            if (j == v) continue;
-            ++nonself;
-            nk += lds_insert<ST>(keys, vals, LOG2S, a.Cp[j], (ST)a.w[beg + e]);
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            ne += j[k] >= 0 ? 1 : 0;
+            if (c[k] >= 0) {
+                ++nonself;
+                nk += lds_insert<ST>(keys, vals, LOG2S, c[k], w[k]);
+            }
         }
         wave_sync();
-        const int dc = has ? a.Cp[v] : -1;
-        const ST kv = has ? a.K[v] : (ST)0;
+        int kk[SPL];
+        ST xx[SPL], sg[SPL];
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            kk[q] = keys[gl + q * G];
+            xx[q] = vals[gl + q * G];
+        }
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            if (kk[q] >= 0) {
+                keys[gl + q * G] = -1;
+                vals[gl + q * G] = 0;
+            }
+            sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
+        }
         SC best = score_min<SC>();
         int bc = INT_MAX;
         ST hd = 0;
-        for (int s = gl; s < S; s += G) {
-            const int k = keys[s];
-            if (k >= 0) {
-                const ST x = vals[s];
-                keys[s] = -1;
-                vals[s] = 0;
-                if (k == dc) {
-                    hd = x;
-                } else {
-                    const SC sc = (SC)a.W * (SC)x - (SC)kv * (SC)a.Sig[k];
-                    if (better(sc, k, best, bc)) {
-                        best = sc;
-                        bc = k;
-                    }
-                }
-            }
-        }
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
         for (int o = G / 2; o > 0; o >>= 1) {
             const SC ob = shfl_xor_t<SC>(best, o);
             const int oc = __shfl_xor(bc, o, 64);
@@ -211,7 +245,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             nonself += __shfl_xor(nonself, o, 64);
         }
         SC gain = 0;
-        const bool mv = has && decide<C>(a, v, dc, kv, best, bc, hd, nonself, &gain);
+        const bool mv = has && decide<C>(a, dc, kv, best, bc, hd, nonself, &gain);
         if (has && gl == 0) {
             ++nv;
             if (mv) {
@@ -220,27 +254,28 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
                 commit<C, FAST>(a, v, dc, bc, kv);
             }
         }
-        if (mv)
-            for (int e = gl; e < d; e += G) a.flags_next[a.tgt[beg + e]] = 1;
+        if (mv) {
+#pragma unroll
+            for (int k = 0; k < E; ++k)
+                if (j[k] >= 0) a.flags_next[j[k]] = 1;
+        }
         wave_sync();
     }
     flush_counters<C>(a, gain_acc, nv, ne, nk, nm);
 }
 
-// Block-wide argmax: every thread passes its (best, bc, hd, nonself); the
-// result is left in the shared slots r_*[0].
-template <typename SC, typename ST>
+// Block-wide argmax over NW wavefronts; the result is left in r.*[0].
+template <typename SC, typename ST, int NW>
 struct BlockRed {
-    SC best[4];
-    int bc[4];
-    ST hd[4];
-    int nonself[4];
+    SC best[NW];
+    int bc[NW];
+    ST hd[NW];
+    int nonself[NW];
     int move;
-    int target;
 };
 
-template <typename SC, typename ST>
-__device__ inline void block_reduce(BlockRed<SC, ST> &r, SC best, int bc, ST hd, int nonself)
+template <typename SC, typename ST, int NW>
+__device__ inline void block_reduce(BlockRed<SC, ST, NW> &r, SC best, int bc, ST hd, int nonself)
 {
     for (int o = 32; o > 0; o >>= 1) {
         const SC ob = shfl_xor_t<SC>(best, o);
@@ -261,7 +296,7 @@ __device__ inline void block_reduce(BlockRed<SC, ST> &r, SC best, int bc, ST hd,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < 4; ++k) {
+        for (int k = 1; k < NW; ++k) {
             if (better(r.best[k], r.bc[k], r.best[0], r.bc[0])) {
                 r.best[0] = r.best[k];
                 r.bc[0] = r.bc[k];
@@ -272,21 +307,23 @@ __device__ inline void block_reduce(BlockRed<SC, ST> &r, SC best, int bc, ST hd,
     }
 }
 
-// Bin 4: one workgroup per vertex, LDS table of the smallest power of two
-// >= 2 * row length (at most 8192 slots).
-template <class C, bool FAST>
-__global__ __launch_bounds__(256) void k_move_block(MoveArgs<C> a)
+// Bins 4-5: one workgroup of BT threads per vertex, LDS table (dynamic shared
+// memory of 2^log2s_max slots) of block_log2s(row length) slots per vertex.
+template <class C, int BT, bool FAST>
+__global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
 {
     typedef typename C::ST ST;
     typedef typename C::SC SC;
-    constexpr int S = 1 << BLOCK_LOG2S_MAX;
-    __shared__ ST s_vals[S];
-    __shared__ int32_t s_keys[S];
-    __shared__ BlockRed<SC, ST> r;
+    constexpr int NW = BT / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ BlockRed<SC, ST, NW> r;
+    const int S_max = 1 << log2s_max;
+    ST *s_vals = (ST *)smem;
+    int32_t *s_keys = (int32_t *)(smem + (size_t)S_max * sizeof(ST));
     if (*a.done) return;
     const int count = *a.count;
     if (count == 0) return;
-    for (int s = threadIdx.x; s < S; s += 256) {
+    for (int s = threadIdx.x; s < S_max; s += BT) {
         s_keys[s] = -1;
         s_vals[s] = 0;
     }
@@ -294,49 +331,58 @@ __global__ __launch_bounds__(256) void k_move_block(MoveArgs<C> a)
     SC gain_acc = 0;
     unsigned long long nv = 0, ne = 0, nk = 0, nm = 0;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        const int v = a.binorder[a.worklist[a.list_begin + idx]];
+        const int v = a.worklist[a.list_begin + idx];
         const int beg = a.off[v];
         const int d = row_len(a.off, a.deg, v);
-        int log2s = 32 - __clz(2 * d - 1);
-        if (log2s < 6) log2s = 6;
-        const int S_eff = 1 << log2s;
-        int nonself = 0;
-        for (int e = threadIdx.x; e < d; e += 256) {
-            const int j = a.tgt[beg + e];
-            ++ne;
-            if (j == v) continue;
-            ++nonself;
-            nk += lds_insert<ST>(s_keys, s_vals, log2s, a.Cp[j], (ST)a.w[beg + e]);
-        }
-        __syncthreads();
         const int dc = a.Cp[v];
         const ST kv = a.K[v];
-        SC best = score_min<SC>();
-        int bc = INT_MAX;
-        ST hd = 0;
-        for (int s = threadIdx.x; s < S_eff; s += 256) {
-            const int k = s_keys[s];
-            if (k >= 0) {
-                const ST x = s_vals[s];
-                s_keys[s] = -1;
-                s_vals[s] = 0;
-                if (k == dc) {
-                    hd = x;
-                } else {
-                    const SC sc = (SC)a.W * (SC)x - (SC)kv * (SC)a.Sig[k];
-                    if (better(sc, k, best, bc)) {
-                        best = sc;
-                        bc = k;
-                    }
+        const int log2s = block_log2s(d);
+        int nonself = 0;
+        for (int e0 = threadIdx.x; e0 < d; e0 += 4 * BT) {
+            int j[4], c[4];
+            ST w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) j[k] = e0 + k * BT < d ? a.tgt[beg + e0 + k * BT] : -1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[k] = j[k] >= 0 ? (ST)a.w[beg + e0 + k * BT] : (ST)0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ne += j[k] >= 0 ? 1 : 0;
+                if (c[k] >= 0) {
+                    ++nonself;
+                    nk += lds_insert<ST>(s_keys, s_vals, log2s, c[k], w[k]);
                 }
             }
         }
-        block_reduce<SC, ST>(r, best, bc, hd, nonself);
+        __syncthreads();
+        SC best = score_min<SC>();
+        int bc = INT_MAX;
+        ST hd = 0;
+        for (int s0 = threadIdx.x; s0 < (1 << log2s); s0 += 4 * BT) {
+            int kk[4];
+            ST xx[4], sg[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int s = s0 + q * BT;
+                kk[q] = s < (1 << log2s) ? s_keys[s] : -1;
+                xx[q] = kk[q] >= 0 ? s_vals[s] : (ST)0;
+                if (kk[q] >= 0) {
+                    s_keys[s] = -1;
+                    s_vals[s] = 0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+        }
+        block_reduce<SC, ST, NW>(r, best, bc, hd, nonself);
         if (threadIdx.x == 0) {
             SC gain = 0;
-            const bool mv = decide<C>(a, v, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0], &gain);
+            const bool mv = decide<C>(a, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0], &gain);
             r.move = mv ? 1 : 0;
-            r.target = r.bc[0];
             ++nv;
             if (mv) {
                 gain_acc += gain;
@@ -346,70 +392,131 @@ __global__ __launch_bounds__(256) void k_move_block(MoveArgs<C> a)
         }
         __syncthreads();
         if (r.move)
-            for (int e = threadIdx.x; e < d; e += 256) a.flags_next[a.tgt[beg + e]] = 1;
+            for (int e = threadIdx.x; e < d; e += BT) a.flags_next[a.tgt[beg + e]] = 1;
         __syncthreads();
     }
     flush_counters<C>(a, gain_acc, nv, ne, nk, nm);
 }
 
-// Bin 5 (hubs): one workgroup per vertex, open-addressing table in HBM at
-// hkeys/hvals + hoff[position in the bin]; the workgroup clears the slots it
-// read, so the table is empty again for the next user.
+// Hubs, step 1: one workgroup per HUB_SLICE-entry slice of a queued hub's row
+// folds the slice into an LDS table, then adds the table into the hub's HBM
+// table (hkeys/hvals + hoff[hub]).
+template <class C>
+__global__ __launch_bounds__(256) void k_move_hub_scatter(MoveArgs<C> a)
+{
+    typedef typename C::ST ST;
+    constexpr int S = 1 << HUB_LOG2S;
+    constexpr int E = HUB_SLICE / 256;
+    __shared__ ST s_vals[S];
+    __shared__ int32_t s_keys[S];
+    if (*a.done) return;
+    const int h = owner_slice(a.hslice, a.nhubs, (int)blockIdx.x);
+    if (!a.hub_act[h]) return;
+    const int v = a.binorder[a.list_begin + h];
+    const int beg = a.off[v];
+    const int d = row_len(a.off, a.deg, v);
+    const int e0 = ((int)blockIdx.x - a.hslice[h]) * HUB_SLICE;
+    for (int s = threadIdx.x; s < S; s += 256) {
+        s_keys[s] = -1;
+        s_vals[s] = 0;
+    }
+    int j[E], c[E];
+    ST w[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int e = e0 + (int)threadIdx.x + k * 256;
+        j[k] = e < d ? a.tgt[beg + e] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) w[k] = j[k] >= 0 ? (ST)a.w[beg + e0 + (int)threadIdx.x + k * 256] : (ST)0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
+    __syncthreads();
+    unsigned long long ne = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        ne += j[k] >= 0 ? 1 : 0;
+        if (c[k] >= 0) lds_insert<ST>(s_keys, s_vals, HUB_LOG2S, c[k], w[k]);
+    }
+    __syncthreads();
+    const int64_t t0 = a.hoff[h];
+    const uint32_t T = (uint32_t)hub_slots(d);
+    for (int s = threadIdx.x; s < S; s += 256) {
+        const int k = s_keys[s];
+        if (k >= 0) hbm_insert<ST>(a.hkeys + t0, a.hvals + t0, T, k, s_vals[s]);
+    }
+    ne = wave_sum_u64(ne);
+    if ((threadIdx.x & 63) == 0 && ne) {
+        atomicAdd(&a.work[1], ne);
+        atomicAdd(a.it_scanned, ne);
+    }
+}
+
+// Hubs, step 2: one workgroup per queued hub takes the argmax over its HBM
+// table, moves, and clears the slots it read so the table is empty again for
+// the next user.
 template <class C, bool FAST>
 __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
 {
     typedef typename C::ST ST;
     typedef typename C::SC SC;
-    __shared__ BlockRed<SC, ST> r;
+    constexpr int NW = HUB_THREADS / 64;
+    __shared__ BlockRed<SC, ST, NW> r;
     if (*a.done) return;
     const int count = *a.count;
     SC gain_acc = 0;
-    unsigned long long nv = 0, ne = 0, nk = 0, nm = 0;
+    unsigned long long nv = 0, nk = 0, nm = 0;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int p = a.worklist[a.list_begin + idx];
+        const int h = p - a.list_begin;
         const int v = a.binorder[p];
         const int beg = a.off[v];
         const int d = row_len(a.off, a.deg, v);
-        const int64_t t0 = a.hoff[p - a.list_begin];
+        const int64_t t0 = a.hoff[h];
         const uint32_t T = (uint32_t)hub_slots(d);
         int32_t *keys = a.hkeys + t0;
         ST *vals = a.hvals + t0;
-        int nonself = 0;
-        for (int e = threadIdx.x; e < d; e += HUB_THREADS) {
-            const int j = a.tgt[beg + e];
-            ++ne;
-            if (j == v) continue;
-            ++nonself;
-            nk += hbm_insert<ST>(keys, vals, T, a.Cp[j], (ST)a.w[beg + e]);
-        }
-        __threadfence_block();
-        __syncthreads();
+        // a hub row holds more than the LDS row limit of distinct targets, so it
+        // always has an entry other than a self-loop
+        const int nonself = threadIdx.x == 0 ? 1 : 0;
+        if (threadIdx.x == 0) a.hub_act[h] = 0;
         const int dc = a.Cp[v];
         const ST kv = a.K[v];
         SC best = score_min<SC>();
         int bc = INT_MAX;
         ST hd = 0;
-        for (uint32_t s = threadIdx.x; s < T; s += HUB_THREADS) {
-            const int k = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (k >= 0) {
-                const ST x = __hip_atomic_load(&vals[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                keys[s] = -1;
-                vals[s] = 0;
-                if (k == dc) {
-                    hd = x;
-                } else {
-                    const SC sc = (SC)a.W * (SC)x - (SC)kv * (SC)a.Sig[k];
-                    if (better(sc, k, best, bc)) {
-                        best = sc;
-                        bc = k;
-                    }
+        for (uint32_t s0 = threadIdx.x; s0 < T; s0 += 4 * HUB_THREADS) {
+            int kk[4];
+            ST xx[4], sg[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t s = s0 + q * HUB_THREADS;
+                kk[q] = s < T ? __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : -1;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t s = s0 + q * HUB_THREADS;
+                xx[q] = kk[q] >= 0 ? __hip_atomic_load(&vals[s], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)
+                                   : (ST)0;
+                sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (kk[q] >= 0) {
+                    const uint32_t s = s0 + q * HUB_THREADS;
+                    keys[s] = -1;
+                    vals[s] = 0;
+                    ++nk;
                 }
+                consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
             }
         }
-        block_reduce<SC, ST>(r, best, bc, hd, nonself);
+        block_reduce<SC, ST, NW>(r, best, bc, hd, nonself);
         if (threadIdx.x == 0) {
             SC gain = 0;
-            const bool mv = decide<C>(a, v, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0], &gain);
+            const bool mv = decide<C>(a, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0], &gain);
             r.move = mv ? 1 : 0;
             ++nv;
             if (mv) {
@@ -424,19 +531,35 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
         __threadfence();
         __syncthreads();
     }
-    flush_counters<C>(a, gain_acc, nv, ne, nk, nm);
+    flush_counters<C>(a, gain_acc, nv, 0, nk, nm);
+}
+
+template <class C, int BT, bool FAST>
+void launch_block(const MoveArgs<C> &a, int grid, int log2s_max, hipStream_t s)
+{
+    const size_t bytes = ((size_t)1 << log2s_max) * (sizeof(typename C::ST) + 4);
+    if (bytes > 65536) {
+        // raise the dynamic-LDS limit of this kernel to what the launch asks for; a
+        // failure shows up as a launch error at the caller's check
+        if (hipFuncSetAttribute((const void *)&k_move_block<C, BT, FAST>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+            hipSuccess)
+            (void)hipGetLastError();
+    }
+    k_move_block<C, BT, FAST><<<grid, BT, bytes, s>>>(a, log2s_max);
 }
 
 template <class C, bool FAST>
-void launch_move_t(int bin, const MoveArgs<C> &a, int grid, hipStream_t s)
+void launch_move_t(int bin, const MoveArgs<C> &a, int grid, int log2s_max, hipStream_t s)
 {
     switch (bin) {
-    case 0: k_move_wave<C, 8, 4, FAST><<<grid, 256, 0, s>>>(a); break;
-    case 1: k_move_wave<C, 32, 6, FAST><<<grid, 256, 0, s>>>(a); break;
-    case 2: k_move_wave<C, 64, 8, FAST><<<grid, 256, 0, s>>>(a); break;
-    case 3: k_move_wave<C, 64, 10, FAST><<<grid, 256, 0, s>>>(a); break;
-    case 4: k_move_block<C, FAST><<<grid, 256, 0, s>>>(a); break;
-    default: k_move_hub<C, FAST><<<grid, HUB_THREADS, 0, s>>>(a); break;
+    case 0: k_move_wave<C, 2, 4, 4, FAST><<<grid, 256, 0, s>>>(a); break;
+    case 1: k_move_wave<C, 8, 4, 6, FAST><<<grid, 256, 0, s>>>(a); break;
+    case 2: k_move_wave<C, 32, 4, 8, FAST><<<grid, 256, 0, s>>>(a); break;
+    case 3: k_move_wave<C, 64, 8, 10, FAST><<<grid, 256, 0, s>>>(a); break;
+    case 4: launch_block<C, 256, FAST>(a, grid, log2s_max, s); break;
+    case 5: launch_block<C, BLOCK_THREADS, FAST>(a, grid, log2s_max, s); break;
+    default: break;  // hubs: launch_move_hubs
     }
 }
 
@@ -444,21 +567,42 @@ void launch_move_t(int bin, const MoveArgs<C> &a, int grid, hipStream_t s)
 
 int move_rows_per_block(int bin)
 {
-    static const int rows[NBINS] = {32, 8, 4, 4, 1, 1};
+    static const int rows[NBINS] = {128, 32, 8, 4, 1, 1, 1};
     return rows[bin];
 }
 
 template <class C>
-void launch_move(int bin, bool fast, const MoveArgs<C> &a, int grid, hipStream_t s)
+void launch_move(int bin, bool fast, const MoveArgs<C> &a, int grid, int log2s_max,
+                 hipStream_t s)
 {
     if (grid <= 0) return;
     if (fast)
-        launch_move_t<C, true>(bin, a, grid, s);
+        launch_move_t<C, true>(bin, a, grid, log2s_max, s);
     else
-        launch_move_t<C, false>(bin, a, grid, s);
+        launch_move_t<C, false>(bin, a, grid, log2s_max, s);
 }
-template void launch_move<CfgNarrow>(int, bool, const MoveArgs<CfgNarrow> &, int, hipStream_t);
-template void launch_move<CfgWideIn>(int, bool, const MoveArgs<CfgWideIn> &, int, hipStream_t);
-template void launch_move<CfgWide>(int, bool, const MoveArgs<CfgWide> &, int, hipStream_t);
+template void launch_move<CfgNarrow>(int, bool, const MoveArgs<CfgNarrow> &, int, int,
+                                     hipStream_t);
+template void launch_move<CfgWideIn>(int, bool, const MoveArgs<CfgWideIn> &, int, int,
+                                     hipStream_t);
+template void launch_move<CfgWide>(int, bool, const MoveArgs<CfgWide> &, int, int, hipStream_t);
+
+template <class C>
+void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t total_slices, int grid,
+                      hipStream_t s)
+{
+    if (total_slices <= 0 || grid <= 0) return;
+    k_move_hub_scatter<C><<<total_slices, 256, 0, s>>>(a);
+    if (fast)
+        k_move_hub<C, true><<<grid, HUB_THREADS, 0, s>>>(a);
+    else
+        k_move_hub<C, false><<<grid, HUB_THREADS, 0, s>>>(a);
+}
+template void launch_move_hubs<CfgNarrow>(bool, const MoveArgs<CfgNarrow> &, int32_t, int,
+                                          hipStream_t);
+template void launch_move_hubs<CfgWideIn>(bool, const MoveArgs<CfgWideIn> &, int32_t, int,
+                                          hipStream_t);
+template void launch_move_hubs<CfgWide>(bool, const MoveArgs<CfgWide> &, int32_t, int,
+                                        hipStream_t);
 
 }  // namespace lv

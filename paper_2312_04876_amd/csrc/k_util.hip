@@ -189,61 +189,108 @@ __device__ inline int len_of(const int32_t *off, const int32_t *deg, int v)
     return deg ? deg[v] : off[v + 1] - off[v];
 }
 
-__global__ __launch_bounds__(256) void k_bin_count(int32_t n, const int32_t *off,
-                                                   const int32_t *deg, int32_t *totals)
-{
-    __shared__ int32_t h[NBINS];
-    if (threadIdx.x < NBINS) h[threadIdx.x] = 0;
-    __syncthreads();
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int b = bin_of(len_of(off, deg, (int)i));
-        if (b >= 0) atomicAdd(&h[b], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x < NBINS && h[threadIdx.x]) atomicAdd(&totals[threadIdx.x], h[threadIdx.x]);
-}
+// ---- degree binning as a stable counting sort over chunks of BIN_CHUNK rows:
+// per-chunk bin counts, one exclusive scan over [bin][chunk], then every chunk
+// writes its rows at its own offsets (no global atomics, deterministic order).
 
-// Append `item` to the list of bin b (wavefront-aggregated atomics); every lane
-// of the wavefront must call this, lanes with b < 0 append nothing.
-__device__ inline void wave_append(int b, int32_t item, const BinInfo &bins, int32_t *cursors,
-                                   int32_t *list)
+__device__ inline unsigned long long lanes_below()
 {
     const int lane = threadIdx.x & 63;
-    unsigned long long todo = __ballot(b >= 0);
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int bl = __shfl(b, leader, 64);
-        const unsigned long long m = __ballot(b == bl);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&cursors[bl], __popcll(m));
-        base = __shfl(base, leader, 64);
-        if (b == bl) list[bins.start[bl] + base + __popcll(m & below)] = item;
-        todo &= ~m;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Per-wavefront bin histogram of one round (one row per lane, b < 0 = none):
+// wcnt[wave][bin] = rows of the wavefront in the bin; returns the lane's rank.
+__device__ inline int wave_bin_rank(int b, int32_t (*wcnt)[NBINS])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long below = lanes_below();
+    int rank = 0;
+    for (int bb = 0; bb < NBINS; ++bb) {
+        const unsigned long long m = __ballot(b == bb);
+        if (b == bb) rank = __popcll(m & below);
+        if (lane == 0) wcnt[wave][bb] = __popcll(m);
     }
+    return rank;
+}
+
+__global__ __launch_bounds__(256) void k_bin_count(int32_t n, const int32_t *off,
+                                                   const int32_t *deg, int32_t *cnt, int32_t G,
+                                                   int32_t lds_max, int32_t *maxlen)
+{
+    __shared__ int32_t h[NBINS];
+    __shared__ int32_t mx[NBINS];
+    __shared__ int32_t wcnt[4][NBINS];
+    if (threadIdx.x < NBINS) {
+        h[threadIdx.x] = 0;
+        mx[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * BIN_CHUNK;
+    for (int r = 0; r < BIN_CHUNK / 256; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        const int len = i < n ? len_of(off, deg, (int)i) : 0;
+        const int b = bin_of(len, lds_max);
+        if (b >= 0) atomicMax(&mx[b], len);
+        wave_bin_rank(b, wcnt);
+        __syncthreads();
+        if (threadIdx.x < NBINS)
+            h[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
+                              wcnt[3][threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x < NBINS) {
+        cnt[threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
+        if (mx[threadIdx.x]) atomicMax(&maxlen[threadIdx.x], mx[threadIdx.x]);
+    }
+}
+
+__global__ void k_bin_starts(const int32_t *boff, int32_t G, int32_t *start)
+{
+    const int b = threadIdx.x;
+    if (b <= NBINS) start[b] = boff[b * G];
 }
 
 __global__ __launch_bounds__(256) void k_bin_fill(int32_t n, const int32_t *off,
-                                                  const int32_t *deg, BinInfo bins,
-                                                  int32_t *cursors, int32_t *binorder)
+                                                  const int32_t *deg, const int32_t *boff,
+                                                  int32_t G, int32_t lds_max, int32_t *binorder)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-        const int64_t i = base + threadIdx.x;
-        const int b = i < n ? bin_of(len_of(off, deg, (int)i)) : -1;
-        wave_append(b, (int32_t)i, bins, cursors, binorder);
+    __shared__ int32_t run[NBINS];
+    __shared__ int32_t wcnt[4][NBINS];
+    if (threadIdx.x < NBINS) run[threadIdx.x] = boff[threadIdx.x * G + blockIdx.x];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * BIN_CHUNK;
+    for (int r = 0; r < BIN_CHUNK / 256; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        const int b = i < n ? bin_of(len_of(off, deg, (int)i), lds_max) : -1;
+        const int rank = wave_bin_rank(b, wcnt);
+        __syncthreads();
+        if (b >= 0) {
+            int pos = run[b] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][b];
+            binorder[pos] = (int32_t)i;
+        }
+        __syncthreads();
+        if (threadIdx.x < NBINS)
+            run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
+                                wcnt[3][threadIdx.x];
+        __syncthreads();
     }
 }
 
 __global__ void k_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
-                            const int32_t *deg, int64_t cap, int64_t *out)
+                            const int32_t *deg, int64_t cap, int64_t *out, int32_t *slices,
+                            int32_t *tslices)
 {
     for (int64_t p = hb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < he;
          p += (int64_t)gridDim.x * blockDim.x) {
-        int64_t d = len_of(off, deg, binorder[p]);
-        if (d > cap) d = cap;
-        out[p - hb] = hub_slots(d);
+        const int64_t len = len_of(off, deg, binorder[p]);
+        const int64_t d = len > cap ? cap : len;
+        const int64_t T = hub_slots(d);
+        out[p - hb] = T;
+        if (slices) slices[p - hb] = (int32_t)((len + HUB_SLICE - 1) / HUB_SLICE);
+        if (tslices) tslices[p - hb] = (int32_t)((T + HUB_SLICE - 1) / HUB_SLICE);
     }
 }
 
@@ -337,12 +384,25 @@ __global__ __launch_bounds__(256) void k_sum_squares(const ST *Sig, int32_t n,
     if ((threadIdx.x & 63) == 0) atomic_add_i128(acc, s);
 }
 
+// Active rows of one round into per-bin worklists: each workgroup takes a chunk
+// of BIN_CHUNK binned rows, counts its active rows per bin, reserves space with
+// one atomic per bin, and writes positions in order.  Active hubs are also
+// flagged for the sliced hub kernels.
 __global__ __launch_bounds__(256) void k_compact(CompactArgs a)
 {
     if (*a.done) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.nb; base += stride) {
-        const int32_t p = (int32_t)(base + threadIdx.x);
+    constexpr int R = BIN_CHUNK / 256;
+    __shared__ int32_t bcnt[NBINS];
+    __shared__ int32_t run[NBINS];
+    __shared__ int32_t wcnt[4][NBINS];
+    if (threadIdx.x < NBINS) bcnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * BIN_CHUNK;
+    int sel[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = base + r * 256 + threadIdx.x;
         int b = -1;
         if (p < a.nb) {
             const int v = a.binorder[p];
@@ -353,9 +413,37 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a)
                 if (a.prune) a.flags[v] = 0;
                 b = 0;
                 while (b + 1 < NBINS && p >= a.bins.start[b + 1]) ++b;
+                if (b == NBINS - 1) a.hub_act[p - a.bins.start[NBINS - 1]] = 1;
             }
         }
-        wave_append(b, p, a.bins, a.counts, a.worklist);
+        sel[r] = b;
+        wave_bin_rank(b, wcnt);
+        __syncthreads();
+        if (threadIdx.x < NBINS)
+            bcnt[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
+                                 wcnt[3][threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x < NBINS)
+        run[threadIdx.x] = bcnt[threadIdx.x] ? atomicAdd(&a.counts[threadIdx.x], bcnt[threadIdx.x]) : 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int b = sel[r];
+        const int rank = wave_bin_rank(b, wcnt);
+        __syncthreads();
+        if (b >= 0) {
+            int pos = a.bins.start[b] + run[b] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][b];
+            // vertex ids for bins 0-4, binorder positions for hubs (their tables are per position)
+            const int32_t p = (int32_t)(base + r * 256 + threadIdx.x);
+            a.worklist[pos] = b == NBINS - 1 ? p : a.binorder[p];
+        }
+        __syncthreads();
+        if (threadIdx.x < NBINS)
+            run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
+                                wcnt[3][threadIdx.x];
+        __syncthreads();
     }
 }
 
@@ -416,27 +504,102 @@ __global__ void k_relabel(int32_t n, int32_t *labels, const int32_t *map)
         labels[i] = map[labels[i]];
 }
 
-__global__ void k_comm_count(int32_t n, const int32_t *Cp, const int32_t *off, const int32_t *deg,
-                             int32_t *ccount, int32_t *ctot)
+// Slot of key c in a 2*COMM_CHUNK-slot LDS table (inserting it if absent).
+__device__ inline int lds_slot(int32_t *keys, int32_t c)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = Cp[i];
-        atomicAdd(&ccount[c], 1);
-        const int d = len_of(off, deg, (int)i);
-        if (d) atomicAdd(&ctot[c], d);
+    constexpr uint32_t mask = 2 * COMM_CHUNK - 1;
+    uint32_t h = hash32((uint32_t)c) >> (32 - COMM_LOG2S);
+    for (;;) {
+        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == c) return (int)h;
+        if (k < 0) {
+            const int32_t old = atomicCAS(&keys[h], -1, c);
+            if (old < 0 || old == c) return (int)h;
+        }
+        h = (h + 1) & mask;
     }
 }
 
-__global__ void k_comm_fill(int32_t n, const int32_t *Cp, const int32_t *coff, int32_t *cursor,
-                            int32_t *members)
+// Members and total degree per community, pre-aggregated per chunk of
+// COMM_CHUNK vertices in LDS so that a large community costs one global atomic
+// per chunk instead of one per member.
+__global__ __launch_bounds__(256) void k_comm_count(int32_t n, const int32_t *Cp, const int32_t *off,
+                                                    const int32_t *deg, int32_t *ccount,
+                                                    int32_t *ctot)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = Cp[i];
-        const int pos = atomicAdd(&cursor[c], 1);
-        members[coff[c] + pos] = (int32_t)i;
+    __shared__ int32_t keys[2 * COMM_CHUNK];
+    __shared__ int32_t cnt[2 * COMM_CHUNK];
+    __shared__ int32_t dsum[2 * COMM_CHUNK];
+    for (int s = threadIdx.x; s < 2 * COMM_CHUNK; s += 256) {
+        keys[s] = -1;
+        cnt[s] = 0;
+        dsum[s] = 0;
     }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * COMM_CHUNK;
+    for (int r = 0; r < COMM_CHUNK / 256; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        if (i < n) {
+            const int s = lds_slot(keys, Cp[i]);
+            atomicAdd(&cnt[s], 1);
+            const int d = len_of(off, deg, (int)i);
+            if (d) atomicAdd(&dsum[s], d);
+        }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < 2 * COMM_CHUNK; s += 256) {
+        const int c = keys[s];
+        if (c >= 0) {
+            atomicAdd(&ccount[c], cnt[s]);
+            if (dsum[s]) atomicAdd(&ctot[c], dsum[s]);
+        }
+    }
+}
+
+// Community-vertex CSR fill: every chunk reserves one range per community it
+// touches and places its members there (rank inside the chunk from LDS).
+__global__ __launch_bounds__(256) void k_comm_fill(int32_t n, const int32_t *Cp, const int32_t *coff,
+                                                   int32_t *cursor, int32_t *members)
+{
+    constexpr int R = COMM_CHUNK / 256;
+    __shared__ int32_t keys[2 * COMM_CHUNK];
+    __shared__ int32_t cnt[2 * COMM_CHUNK];
+    for (int s = threadIdx.x; s < 2 * COMM_CHUNK; s += 256) {
+        keys[s] = -1;
+        cnt[s] = 0;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * COMM_CHUNK;
+    int slot[R], rank[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        slot[r] = -1;
+        rank[r] = 0;
+        if (i < n) {
+            slot[r] = lds_slot(keys, Cp[i]);
+            rank[r] = atomicAdd(&cnt[slot[r]], 1);
+        }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < 2 * COMM_CHUNK; s += 256) {
+        const int c = keys[s];
+        if (c >= 0) cnt[s] = coff[c] + atomicAdd(&cursor[c], cnt[s]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        if (i < n) members[cnt[slot[r]] + rank[r]] = (int32_t)i;
+    }
+}
+
+__global__ void k_member_degrees(int32_t n, const int32_t *members, const int32_t *off,
+                                 const int32_t *deg, int32_t *mdeg)
+{
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n;
+         m += (int64_t)gridDim.x * blockDim.x)
+        mdeg[m] = len_of(off, deg, members[m]);
 }
 
 }  // namespace
@@ -503,31 +666,46 @@ void launch_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, ui
                                                          (unsigned char *)Sig, sbytes);
 }
 
-void launch_bin_count(int32_t n, const int32_t *off, const int32_t *deg, int32_t *totals,
-                      hipStream_t s)
+int32_t bin_chunks(int32_t n) { return (int32_t)(((int64_t)n + BIN_CHUNK - 1) / BIN_CHUNK); }
+
+void launch_bin_count(int32_t n, const int32_t *off, const int32_t *deg, int32_t lds_max,
+                      int32_t *cnt, int32_t *boff, int64_t *scratch, int32_t *starts,
+                      int32_t *maxlen, hipStream_t s)
 {
-    if (n > 0) k_bin_count<<<grid_for(n, 256, 2048), 256, 0, s>>>(n, off, deg, totals);
+    const int32_t G = bin_chunks(n);
+    k_fill_i32<<<1, 64, 0, s>>>(maxlen, 0, NBINS);
+    if (G > 0) k_bin_count<<<G, 256, 0, s>>>(n, off, deg, cnt, G, lds_max, maxlen);
+    launch_exclusive_scan<int32_t, int32_t>(cnt, boff, (int64_t)NBINS * G, scratch, nullptr, s);
+    k_bin_starts<<<1, 64, 0, s>>>(boff, G, starts);
 }
 
-void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, BinInfo bins,
-                     int32_t *cursors, int32_t *binorder, hipStream_t s)
+void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, int32_t lds_max,
+                     const int32_t *boff, int32_t *binorder, hipStream_t s)
 {
-    if (n > 0)
-        k_bin_fill<<<grid_for(n, 256, 2048), 256, 0, s>>>(n, off, deg, bins, cursors, binorder);
+    const int32_t G = bin_chunks(n);
+    if (G > 0) k_bin_fill<<<G, 256, 0, s>>>(n, off, deg, boff, G, lds_max, binorder);
 }
 
 void launch_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
-                      const int32_t *deg, int64_t cap, int64_t *out, hipStream_t s)
+                      const int32_t *deg, int64_t cap, int64_t *out, int32_t *slices,
+                      int32_t *tslices, hipStream_t s)
 {
     if (he > hb)
-        k_hub_sizes<<<grid_for(he - hb, 256), 256, 0, s>>>(binorder, hb, he, off, deg, cap, out);
+        k_hub_sizes<<<grid_for(he - hb, 256), 256, 0, s>>>(binorder, hb, he, off, deg, cap, out,
+                                                           slices, tslices);
+}
+
+void launch_member_degrees(int32_t n, const int32_t *members, const int32_t *off,
+                           const int32_t *deg, int32_t *mdeg, hipStream_t s)
+{
+    if (n > 0) k_member_degrees<<<grid_for(n, 256), 256, 0, s>>>(n, members, off, deg, mdeg);
 }
 
 template <class C>
 void launch_row_reduce(int bin, int op, const RowArgs<C> &a, hipStream_t s)
 {
     if (a.count <= 0) return;
-    const int rows_per_block[NBINS] = {32, 8, 4, 4, 1, 1};
+    const int rows_per_block[NBINS] = {32, 8, 4, 4, 1, 1, 1};
     const int grid = grid_for(a.count, rows_per_block[bin], 4096);
 #define LV_ROW(G)                                                            \
     do {                                                                     \
@@ -561,7 +739,7 @@ template void launch_sum_squares<int64_t>(const int64_t *, int32_t, unsigned lon
 
 void launch_compact(const CompactArgs &a, hipStream_t s)
 {
-    if (a.nb > 0) k_compact<<<grid_for(a.nb, 256, 4096), 256, 0, s>>>(a);
+    if (a.nb > 0) k_compact<<<bin_chunks(a.nb), 256, 0, s>>>(a);
 }
 
 template <typename ST>
@@ -603,13 +781,17 @@ void launch_relabel(int32_t n, int32_t *labels, const int32_t *map, hipStream_t 
 void launch_comm_count(int32_t n, const int32_t *Cp, const int32_t *off, const int32_t *deg,
                        int32_t *ccount, int32_t *ctot, hipStream_t s)
 {
-    if (n > 0) k_comm_count<<<grid_for(n, 256), 256, 0, s>>>(n, Cp, off, deg, ccount, ctot);
+    if (n > 0)
+        k_comm_count<<<(unsigned)(((int64_t)n + COMM_CHUNK - 1) / COMM_CHUNK), 256, 0, s>>>(
+            n, Cp, off, deg, ccount, ctot);
 }
 
 void launch_comm_fill(int32_t n, const int32_t *Cp, const int32_t *coff, int32_t *cursor,
                       int32_t *members, hipStream_t s)
 {
-    if (n > 0) k_comm_fill<<<grid_for(n, 256), 256, 0, s>>>(n, Cp, coff, cursor, members);
+    if (n > 0)
+        k_comm_fill<<<(unsigned)(((int64_t)n + COMM_CHUNK - 1) / COMM_CHUNK), 256, 0, s>>>(
+            n, Cp, coff, cursor, members);
 }
 
 }  // namespace lv

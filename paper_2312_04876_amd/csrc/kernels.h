@@ -34,17 +34,31 @@ void launch_validate(int32_t n, int64_t nnz, const int32_t *off, const int32_t *
 void launch_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,
                           void *K, void *Sig, int sbytes, hipStream_t s);
 
-// Degree binning: count rows per bin into totals[0..NBINS), then fill binorder.
-// Row length: deg[v] if deg, else off[v+1]-off[v].
-void launch_bin_count(int32_t n, const int32_t *off, const int32_t *deg, int32_t *totals,
-                      hipStream_t s);
-void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, BinInfo bins,
-                     int32_t *cursors, int32_t *binorder, hipStream_t s);
+// Degree binning as a stable counting sort over chunks of BIN_CHUNK rows.
+// Row length: deg[v] if deg, else off[v+1]-off[v].  launch_bin_count writes
+// per-chunk bin counts (cnt, NBINS * bin_chunks(n)), their exclusive scan
+// (boff, one more element) and the bin boundaries starts[0..NBINS] (device);
+// launch_bin_fill then writes binorder.
+// lds_max is the LDS row limit L of the bins; maxlen[0..NBINS) receives the
+// longest row of every bin.
+int32_t bin_chunks(int32_t n);
+void launch_bin_count(int32_t n, const int32_t *off, const int32_t *deg, int32_t lds_max,
+                      int32_t *cnt, int32_t *boff, int64_t *scratch, int32_t *starts,
+                      int32_t *maxlen, hipStream_t s);
+void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, int32_t lds_max,
+                     const int32_t *boff, int32_t *binorder, hipStream_t s);
 
-// HBM table sizes of the rows binorder[hb .. he): out[p-hb] = hub_slots(len),
-// len capped at cap (aggregation caps a community's table at |Gamma|).
+// For the rows binorder[hb .. he): HBM table sizes out[p-hb] = hub_slots(len
+// capped at cap) (aggregation caps a community's table at |Gamma|), and when
+// non-null the number of HUB_SLICE slices of the row (slices) and of the
+// table (tslices).
 void launch_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
-                      const int32_t *deg, int64_t cap, int64_t *out, hipStream_t s);
+                      const int32_t *deg, int64_t cap, int64_t *out, int32_t *slices,
+                      int32_t *tslices, hipStream_t s);
+
+// mdeg[m] = row length of members[m].
+void launch_member_degrees(int32_t n, const int32_t *members, const int32_t *off,
+                           const int32_t *deg, int32_t *mdeg, hipStream_t s);
 
 // Row reductions over the rows of one bin.
 //   op 0: K[v] = Sigma[v] = sum of row weights
@@ -75,8 +89,9 @@ struct CompactArgs {
     int32_t prune;
     int32_t round, round_bits, pass, it;
     uint64_t seed;
-    int32_t *worklist;  // positions into binorder, grouped by bin at bins.start[b]
+    int32_t *worklist;  // per bin at bins.start[b]: vertex ids (bins 0-4), binorder positions (hubs)
     int32_t *counts;    // per-bin count of this round (zero on entry)
+    uint8_t *hub_act;   // per hub (position - bins.start[NBINS-1]): queued this round
     const int32_t *done;
 };
 void launch_compact(const CompactArgs &a, hipStream_t s);
@@ -96,7 +111,10 @@ struct MoveArgs {
     int32_t *mv_v, *mv_c, *mv_count;   // deferred moves (deterministic mode)
     int32_t *hkeys;                    // HBM tables of the hub bin
     typename C::ST *hvals;
-    const int64_t *hoff;
+    const int64_t *hoff;               // table offset per hub
+    const int32_t *hslice;             // first slice per hub (exclusive scan, nhubs + 1)
+    uint8_t *hub_act;                  // hub queued in this round
+    int32_t nhubs;
     unsigned long long *sumN;          // 128-bit gain sum of this iteration
     unsigned long long *work;          // [vertices, entries, keys, moves]
     unsigned long long *it_moves, *it_scanned;
@@ -104,10 +122,17 @@ struct MoveArgs {
     int64_t W;
     int32_t rule;                      // min-label rule for singleton moves
 };
-// grid: workgroups to launch for this bin (each loops over the device count)
+// Bins 0-4; grid: workgroups to launch for this bin (each loops over the device count);
+// log2s_max: LDS table size of bin 4 (block_log2s of the bin's longest row).
 template <class C>
-void launch_move(int bin, bool fast, const MoveArgs<C> &a, int grid, hipStream_t s);
+void launch_move(int bin, bool fast, const MoveArgs<C> &a, int grid, int log2s_max,
+                 hipStream_t s);
 int move_rows_per_block(int bin);
+// Hub bin: one workgroup per row slice (all hubs' slices, inactive ones exit),
+// then one workgroup per queued hub for the argmax and the move.
+template <class C>
+void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t total_slices, int grid,
+                      hipStream_t s);
 
 // Deferred moves of a round (deterministic mode).
 template <typename ST>
@@ -143,13 +168,20 @@ struct AggArgs {
     int32_t *hkeys;
     typename C::ST *hvals;
     const int64_t *hoff;
+    const int32_t *mpre;              // hub bin: exclusive scan of member row lengths
+    const int32_t *cslice, *tslice;   // hub bin: first row slice / table slice per community
+    int32_t ncomm;                    // |Gamma| (caps hub table sizes)
     unsigned long long *work;         // [communities, members, entries, emitted]
 };
 // Bins 0-4 (LDS tables); the hub bin goes through launch_aggregate_hub.
+// log2s_max: LDS table size of bin 4.
 template <class C>
-void launch_aggregate(int bin, const AggArgs<C> &a, hipStream_t s);
-// Bin 5: HBM tables of hub_slots(min(total degree, ncomm)) slots at hoff[index in bin].
+void launch_aggregate(int bin, const AggArgs<C> &a, int log2s_max, hipStream_t s);
+// Bin 5: HBM tables of hub_slots(min(total degree, ncomm)) slots at hoff[index in bin];
+// one workgroup per HUB_SLICE entries of a community's member rows, then one per
+// HUB_SLICE table slots to write the row.
 template <class C>
-void launch_aggregate_hub(const AggArgs<C> &a, int32_t ncomm, hipStream_t s);
+void launch_aggregate_hub(const AggArgs<C> &a, int32_t row_slices, int32_t table_slices,
+                          hipStream_t s);
 
 }  // namespace lv

@@ -32,6 +32,7 @@ struct Layout {
     size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hkeys, hvals, hsz, hoff, scratch;
+    size_t bincnt, binoff, slA, slB, mpre, hub_act;
 };
 
 Layout make_layout(int32_t n, int64_t nnz, int sb)
@@ -82,6 +83,13 @@ Layout make_layout(int32_t n, int64_t nnz, int sb)
     L.hsz = take(8 * (n1 + 1));
     L.hoff = take(8 * (n1 + 1));
     L.scratch = take(8 * (size_t)L.scratch_elems);
+    const size_t nchunks = (size_t)bin_chunks(n) + 1;
+    L.bincnt = take(4 * ((size_t)NBINS * nchunks + 8));
+    L.binoff = take(4 * ((size_t)NBINS * nchunks + 8));
+    L.slA = take(4 * (n1 + 1));
+    L.slB = take(4 * (n1 + 1));
+    L.mpre = take(4 * (n1 + 1));
+    L.hub_act = take(n1);
     L.total = cur;
     return L;
 }
@@ -99,9 +107,9 @@ struct LevelH {
 
 // Kernel families timed with HIP events when profiling.
 enum Fam {
-    F_MOVE0 = 0,  // .. F_MOVE0 + 5
-    F_AGG0 = 6,   // .. F_AGG0 + 5
-    F_COMPACT = 12,
+    F_MOVE0 = 0,       // .. F_MOVE0 + NBINS - 1
+    F_AGG0 = NBINS,    // .. F_AGG0 + NBINS - 1
+    F_COMPACT = 2 * NBINS,
     F_APPLY,
     F_ITER,
     F_SETUP,
@@ -110,10 +118,12 @@ enum Fam {
     F_COUNT
 };
 const char *FAM_NAMES[F_COUNT] = {
-    "move_bin0_8lanes", "move_bin1_32lanes", "move_bin2_wave", "move_bin3_wave",
-    "move_bin4_block", "move_bin5_hub", "agg_bin0_8lanes", "agg_bin1_32lanes",
-    "agg_bin2_wave", "agg_bin3_wave", "agg_bin4_block", "agg_bin5_hub",
-    "compact", "apply", "iteration_end", "level_setup", "aggregate_prep", "final"};
+    "move_bin0_2lanes", "move_bin1_8lanes", "move_bin2_32lanes", "move_bin3_wave",
+    "move_bin4_block", "move_bin5_bigblock", "move_bin6_hub", "agg_bin0_8lanes",
+    "agg_bin1_32lanes", "agg_bin2_wave", "agg_bin3_wave", "agg_bin4_block",
+    "agg_bin5_bigblock", "agg_bin6_hub", "compact", "apply", "iteration_end", "level_setup",
+    "aggregate_prep", "final"};
+static_assert(F_COUNT == 2 * NBINS + 6, "family names");
 
 struct Pending {
     int fam;
@@ -145,8 +155,13 @@ struct louvain_ctx {
     int32_t *hkeys;
     void *hvals;
     int64_t *hsz, *hoff, *scratch;
+    int32_t *bincnt, *binoff, *slA, *slB, *mpre;
+    uint8_t *hub_act;
+    int32_t hub_slices;  // row slices of the current level's hubs
     int64_t W;
     bool wide;
+    int32_t lds_max;     // LDS row limit of the bins (LDS_MAX_NARROW or LDS_MAX_WIDE)
+    int32_t bin_maxlen[NBINS];
     int state;
     int pass;
     double tau;
@@ -265,21 +280,27 @@ int setup_level(louvain_ctx *ctx)
     launch_fill_bytes_zero(ctx->sc, offsetof(DevScalars, err), s);
     CKL();
     launch_init_vertices(l.n, ctx->Cp, ctx->size, ctx->fa, ctx->fb, ctx->K, ctx->Sig, ctx->L.sb, s);
-    launch_bin_count(l.n, l.off, l.deg, ctx->sc->bin_total, s);
+    launch_bin_count(l.n, l.off, l.deg, ctx->lds_max, ctx->bincnt, ctx->binoff, ctx->scratch,
+                     ctx->sc->bin_start, ctx->sc->bin_maxlen, s);
     CKL();
     TRY(prof_end(ctx, F_SETUP, ev));
     TRY(read_scalars(ctx));
-    ctx->bins.start[0] = 0;
-    for (int b = 0; b < NBINS; ++b) ctx->bins.start[b + 1] = ctx->bins.start[b] + ctx->hsc->bin_total[b];
+    for (int b = 0; b <= NBINS; ++b) ctx->bins.start[b] = ctx->hsc->bin_start[b];
+    for (int b = 0; b < NBINS; ++b) ctx->bin_maxlen[b] = ctx->hsc->bin_maxlen[b];
     ctx->nb = ctx->bins.start[NBINS];
     TRY(prof_begin(ctx, &ev));
-    launch_bin_fill(l.n, l.off, l.deg, ctx->bins, ctx->sc->bin_cursor, ctx->binorder, s);
+    launch_bin_fill(l.n, l.off, l.deg, ctx->lds_max, ctx->binoff, ctx->binorder, s);
     CKL();
     const int hubs = bins_of(ctx, NBINS - 1);
+    ctx->hub_slices = 0;
     if (hubs > 0) {
+        // HBM table offsets and row slices of the hubs (cursor is free during moving)
         launch_hub_sizes(ctx->binorder, ctx->bins.start[NBINS - 1], ctx->bins.start[NBINS], l.off,
-                         l.deg, INT64_MAX, ctx->hsz, s);
+                         l.deg, INT64_MAX, ctx->hsz, ctx->cursor, nullptr, s);
         launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
+        launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->slA, hubs, ctx->scratch,
+                                                &ctx->sc->hub_slices, s);
+        launch_fill_u8(ctx->hub_act, 0, hubs, s);
         CKL();
     }
     for (int b = 0; b < NBINS; ++b) {
@@ -299,6 +320,10 @@ int setup_level(louvain_ctx *ctx)
         CKL();
     }
     TRY(prof_end(ctx, F_SETUP, ev));
+    if (hubs > 0) {
+        TRY(read_scalars(ctx));
+        ctx->hub_slices = (int32_t)ctx->hsc->hub_slices;
+    }
     return LOUVAIN_OK;
 }
 
@@ -330,16 +355,20 @@ int move_phase(louvain_ctx *ctx)
     a.hkeys = ctx->hkeys;
     a.hvals = (ST *)ctx->hvals;
     a.hoff = ctx->hoff;
+    a.hslice = ctx->slA;
+    a.hub_act = ctx->hub_act;
+    a.nhubs = bins_of(ctx, NBINS - 1);
     a.done = &ctx->sc->done;
     a.W = ctx->W;
     a.rule = 1;
-    int grid[NBINS];
+    int grid[NBINS], log2s[NBINS];
     for (int b = 0; b < NBINS; ++b) {
         const int cnt = bins_of(ctx, b);
         const int per = move_rows_per_block(b);
         int g = (cnt + per - 1) / per;
         const int cap = b >= 4 ? 1024 : 2048;
         grid[b] = std::min(g, cap);
+        log2s[b] = block_log2s(ctx->bin_maxlen[b]);
     }
     int it;
     for (it = 0; it < max_it; ++it) {
@@ -363,6 +392,7 @@ int move_phase(louvain_ctx *ctx)
             ca.seed = ctx->p.seed;
             ca.worklist = ctx->worklist;
             ca.counts = ctx->sc->bin_count;
+            ca.hub_act = ctx->hub_act;
             ca.done = &ctx->sc->done;
             hipEvent_t ev;
             TRY(prof_begin(ctx, &ev));
@@ -375,7 +405,10 @@ int move_phase(louvain_ctx *ctx)
                 a.count = &ctx->sc->bin_count[b];
                 a.work = ctx->sc->work[WORK_MOVE + b];
                 TRY(prof_begin(ctx, &ev));
-                launch_move<C>(b, fast, a, grid[b], s);
+                if (b < NBINS - 1)
+                    launch_move<C>(b, fast, a, grid[b], log2s[b], s);
+                else
+                    launch_move_hubs<C>(fast, a, ctx->hub_slices, grid[b], s);
                 CKL();
                 TRY(prof_end(ctx, F_MOVE0 + b, ev));
             }
@@ -489,26 +522,41 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
     launch_fill_i32(ctx->cursor, 0, nc, s);
     launch_comm_fill(l.n, ctx->Cp, ctx->coff, ctx->cursor, ctx->members, s);
     // bins of communities by total degree
-    launch_fill_i32(ctx->sc->bin_total, 0, 8, s);
-    launch_fill_i32(ctx->sc->bin_cursor, 0, 8, s);
-    launch_bin_count(nc, nullptr, ctx->ctot, ctx->sc->bin_total, s);
+    launch_bin_count(nc, nullptr, ctx->ctot, ctx->lds_max, ctx->bincnt, ctx->binoff, ctx->scratch,
+                     ctx->sc->bin_start, ctx->sc->bin_maxlen, s);
     launch_fill_i32(ydeg, 0, nc, s);
     CKL();
     TRY(prof_end(ctx, F_AGGPREP, ev));
     TRY(read_scalars(ctx));
     BinInfo cb;
-    cb.start[0] = 0;
-    for (int b = 0; b < NBINS; ++b) cb.start[b + 1] = cb.start[b] + ctx->hsc->bin_total[b];
+    for (int b = 0; b <= NBINS; ++b) cb.start[b] = ctx->hsc->bin_start[b];
     TRY(prof_begin(ctx, &ev));
-    launch_bin_fill(nc, nullptr, ctx->ctot, cb, ctx->sc->bin_cursor, ctx->cbinorder, s);
+    int cmax[NBINS];
+    for (int b = 0; b < NBINS; ++b) cmax[b] = ctx->hsc->bin_maxlen[b];
+    launch_bin_fill(nc, nullptr, ctx->ctot, ctx->lds_max, ctx->binoff, ctx->cbinorder, s);
     const int hubs = cb.start[NBINS] - cb.start[NBINS - 1];
+    int32_t row_slices = 0, table_slices = 0;
     if (hubs > 0) {
+        // member row lengths prefix (windows of hub communities), HBM table
+        // offsets, row slices (in cursor) and table slices (in ccount)
+        launch_member_degrees(l.n, ctx->members, l.off, l.deg, ctx->cursor, s);
+        launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->mpre, l.n, ctx->scratch, nullptr,
+                                                s);
         launch_hub_sizes(ctx->cbinorder, cb.start[NBINS - 1], cb.start[NBINS], nullptr, ctx->ctot,
-                         nc, ctx->hsz, s);
+                         nc, ctx->hsz, ctx->cursor, ctx->ccount, s);
         launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
+        launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->slA, hubs, ctx->scratch,
+                                                &ctx->sc->hub_slices, s);
+        launch_exclusive_scan<int32_t, int32_t>(ctx->ccount, ctx->slB, hubs, ctx->scratch,
+                                                &ctx->sc->hub_tslices, s);
     }
     CKL();
     TRY(prof_end(ctx, F_AGGPREP, ev));
+    if (hubs > 0) {
+        TRY(read_scalars(ctx));
+        row_slices = (int32_t)ctx->hsc->hub_slices;
+        table_slices = (int32_t)ctx->hsc->hub_tslices;
+    }
     unsigned long long emitted0 = 0;
     for (int b = 0; b < NBINS; ++b) emitted0 += ctx->hsc->work[WORK_AGG + b][3];
     AggArgs<C> g;
@@ -527,6 +575,10 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
     g.hkeys = ctx->hkeys;
     g.hvals = (ST *)ctx->hvals;
     g.hoff = ctx->hoff;
+    g.mpre = ctx->mpre;
+    g.cslice = ctx->slA;
+    g.tslice = ctx->slB;
+    g.ncomm = nc;
     for (int b = 0; b < NBINS; ++b) {
         g.begin = cb.start[b];
         g.count = cb.start[b + 1] - cb.start[b];
@@ -534,9 +586,9 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
         g.work = ctx->sc->work[WORK_AGG + b];
         TRY(prof_begin(ctx, &ev));
         if (b < NBINS - 1)
-            launch_aggregate<C>(b, g, s);
+            launch_aggregate<C>(b, g, block_log2s(cmax[b]), s);
         else
-            launch_aggregate_hub<C>(g, nc, s);
+            launch_aggregate_hub<C>(g, row_slices, table_slices, s);
         CKL();
         TRY(prof_end(ctx, F_AGG0 + b, ev));
     }
@@ -763,6 +815,7 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     if (W >= (1ull << 62)) return fail(LOUVAIN_EOVERFLOW);
     ctx->W = (int64_t)W;
     ctx->wide = W >= (1ull << 31);
+    ctx->lds_max = ctx->wide ? LDS_MAX_WIDE : LDS_MAX_NARROW;
     ctx->L = make_layout(n, nnz, ctx->wide ? 8 : 4);
     if (workspace_bytes < ctx->L.total) return fail(LOUVAIN_ENOSPC);
     const Layout &L = ctx->L;
@@ -800,6 +853,12 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     ctx->hsz = (int64_t *)(b + L.hsz);
     ctx->hoff = (int64_t *)(b + L.hoff);
     ctx->scratch = (int64_t *)(b + L.scratch);
+    ctx->bincnt = (int32_t *)(b + L.bincnt);
+    ctx->binoff = (int32_t *)(b + L.binoff);
+    ctx->slA = (int32_t *)(b + L.slA);
+    ctx->slB = (int32_t *)(b + L.slB);
+    ctx->mpre = (int32_t *)(b + L.mpre);
+    ctx->hub_act = b + L.hub_act;
     // the scalar block keeps W; the hash slab starts empty and every user clears what it used
     launch_init_hash_slab(ctx->hkeys, ctx->hvals, L.slots, L.sb, ctx->s);
     launch_iota(ctx->top, n, ctx->s);
