@@ -58,9 +58,9 @@ def parse():
 
 # Kernel family (as named by louvain_kernel_stats) -> the device kernels of one launch.
 FAMILY_KERNELS = {
-    "move_bin0_2lanes": [r"k_move_wave<[^>]*>, 2, 4, 4,"],
-    "move_bin1_8lanes": [r"k_move_wave<[^>]*>, 8, 4, 6,"],
-    "move_bin2_32lanes": [r"k_move_wave<[^>]*>, 32, 4, 8,"],
+    "move_bin0_1lane": [r"k_move_wave<[^>]*>, 1, 8, 4,"],
+    "move_bin1_4lanes": [r"k_move_wave<[^>]*>, 4, 8, 6,"],
+    "move_bin2_16lanes": [r"k_move_wave<[^>]*>, 16, 8, 8,"],
     "move_bin3_wave": [r"k_move_wave<[^>]*>, 64, 8, 10,"],
     "move_bin4_block": [r"k_move_block<[^>]*>, 256,"],
     "move_bin5_bigblock": [r"k_move_block<[^>]*>, 512,"],

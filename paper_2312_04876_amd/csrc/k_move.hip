@@ -155,30 +155,58 @@ __device__ inline void consider(const MoveArgs<C> &a, int dc, typename C::ST kv,
     }
 }
 
-// Bins 0-3: G lanes per vertex (64/G vertices per wavefront), each lane
-// holding up to E entries of the row, LDS table of 2^LOG2S slots per group.
+// Insert (c, w) into a power-of-two LDS table; returns the slot, and sets
+// *fresh when c was a new key.
+template <typename ST>
+__device__ inline int lds_insert_slot(int32_t *keys, ST *vals, int log2s, int32_t c, ST w,
+                                      int *fresh)
+{
+    const uint32_t mask = (1u << log2s) - 1u;
+    uint32_t h = hash32((uint32_t)c) >> (32 - log2s);
+    for (;;) {
+        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == c) {
+            atomic_add_t<ST>(&vals[h], w);
+            return (int)h;
+        }
+        if (k < 0) {
+            const int32_t old = atomicCAS(&keys[h], -1, c);
+            if (old < 0 || old == c) {
+                atomic_add_t<ST>(&vals[h], w);
+                *fresh += old < 0 ? 1 : 0;
+                return (int)h;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Bins 0-3: G lanes per vertex (64/G vertices per wavefront), lane l holding
+// entries l, l+G, ... (up to E of them), LDS table of 2^LOG2S slots per group
+// (groups padded by one slot to spread LDS banks).  Each lane scores the
+// communities of its own entries from the slots it inserted into, so the
+// table is never scanned; duplicates score the same candidate twice.
 template <class C, int G, int E, int LOG2S, bool FAST>
 __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
 {
     typedef typename C::ST ST;
     typedef typename C::SC SC;
     constexpr int S = 1 << LOG2S;
+    constexpr int SP = S + 1;  // padded group stride
     constexpr int GPW = 64 / G;
     constexpr int NG = 4 * GPW;
-    constexpr int SPL = S / G;  // table slots scanned per lane
-    __shared__ ST s_vals[NG * S];
-    __shared__ int32_t s_keys[NG * S];
+    __shared__ ST s_vals[NG * SP];
+    __shared__ int32_t s_keys[NG * SP];
     if (*a.done) return;
     const int count = *a.count;
     if (count == 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / G, gl = lane % G;
-    int32_t *keys = s_keys + (wave * GPW + grp) * S;
-    ST *vals = s_vals + (wave * GPW + grp) * S;
-#pragma unroll
-    for (int q = 0; q < SPL; ++q) {
-        keys[gl + q * G] = -1;
-        vals[gl + q * G] = 0;
+    int32_t *keys = s_keys + (wave * GPW + grp) * SP;
+    ST *vals = s_vals + (wave * GPW + grp) * SP;
+    for (int q = gl; q < S; q += G) {
+        keys[q] = -1;
+        vals[q] = 0;
     }
     wave_sync();
     SC gain_acc = 0;
@@ -196,44 +224,56 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             dc = a.Cp[v];
             kv = a.K[v];
         }
-        int j[E], c[E];
+        int j[E], c[E], slot[E];
         ST w[E];
 #pragma unroll
-        for (int k = 0; k < E; ++k) j[k] = (gl + k * G < d) ? a.tgt[beg + gl + k * G] : -1;
-#pragma unroll
-        for (int k = 0; k < E; ++k) w[k] = (j[k] >= 0) ? (ST)a.w[beg + gl + k * G] : (ST)0;
+        for (int k = 0; k < E; ++k) {
+            const bool in = gl + k * G < d;
+            j[k] = in ? a.tgt[beg + gl + k * G] : -1;
+            w[k] = in ? (ST)a.w[beg + gl + k * G] : (ST)0;
+        }
 #pragma unroll
         for (int k = 0; k < E; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
-        int nonself = 0;
+        int nonself = 0, fresh = 0;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             ne += j[k] >= 0 ? 1 : 0;
+            slot[k] = -1;
             if (c[k] >= 0) {
                 ++nonself;
-                nk += lds_insert<ST>(keys, vals, LOG2S, c[k], w[k]);
+                slot[k] = lds_insert_slot<ST>(keys, vals, LOG2S, c[k], w[k], &fresh);
             }
         }
+        nk += fresh;
         wave_sync();
-        int kk[SPL];
-        ST xx[SPL], sg[SPL];
+        ST x[E], sg[E];
 #pragma unroll
-        for (int q = 0; q < SPL; ++q) {
-            kk[q] = keys[gl + q * G];
-            xx[q] = vals[gl + q * G];
-        }
+        for (int k = 0; k < E; ++k) x[k] = slot[k] >= 0 ? vals[slot[k]] : (ST)0;
 #pragma unroll
-        for (int q = 0; q < SPL; ++q) {
-            if (kk[q] >= 0) {
-                keys[gl + q * G] = -1;
-                vals[gl + q * G] = 0;
-            }
-            sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
-        }
+        for (int k = 0; k < E; ++k) sg[k] = (c[k] >= 0 && c[k] != dc) ? a.Sig[c[k]] : (ST)0;
         SC best = score_min<SC>();
         int bc = INT_MAX;
         ST hd = 0;
 #pragma unroll
-        for (int q = 0; q < SPL; ++q) consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+        for (int k = 0; k < E; ++k) {
+            if (c[k] < 0) continue;
+            if (c[k] == dc) {
+                hd = x[k];
+            } else {
+                const SC sc = (SC)a.W * (SC)x[k] - (SC)kv * (SC)sg[k];
+                if (better(sc, c[k], best, bc)) {
+                    best = sc;
+                    bc = c[k];
+                }
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if (slot[k] >= 0) {
+                keys[slot[k]] = -1;
+                vals[slot[k]] = 0;
+            }
         for (int o = G / 2; o > 0; o >>= 1) {
             const SC ob = shfl_xor_t<SC>(best, o);
             const int oc = __shfl_xor(bc, o, 64);
@@ -241,7 +281,8 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
                 best = ob;
                 bc = oc;
             }
-            hd += shfl_xor_t<ST>(hd, o);
+            const ST oh = shfl_xor_t<ST>(hd, o);
+            hd = oh > hd ? oh : hd;  // lanes that saw the own community hold the same total
             nonself += __shfl_xor(nonself, o, 64);
         }
         SC gain = 0;
@@ -553,9 +594,9 @@ template <class C, bool FAST>
 void launch_move_t(int bin, const MoveArgs<C> &a, int grid, int log2s_max, hipStream_t s)
 {
     switch (bin) {
-    case 0: k_move_wave<C, 2, 4, 4, FAST><<<grid, 256, 0, s>>>(a); break;
-    case 1: k_move_wave<C, 8, 4, 6, FAST><<<grid, 256, 0, s>>>(a); break;
-    case 2: k_move_wave<C, 32, 4, 8, FAST><<<grid, 256, 0, s>>>(a); break;
+    case 0: k_move_wave<C, 1, 8, 4, FAST><<<grid, 256, 0, s>>>(a); break;
+    case 1: k_move_wave<C, 4, 8, 6, FAST><<<grid, 256, 0, s>>>(a); break;
+    case 2: k_move_wave<C, 16, 8, 8, FAST><<<grid, 256, 0, s>>>(a); break;
     case 3: k_move_wave<C, 64, 8, 10, FAST><<<grid, 256, 0, s>>>(a); break;
     case 4: launch_block<C, 256, FAST>(a, grid, log2s_max, s); break;
     case 5: launch_block<C, BLOCK_THREADS, FAST>(a, grid, log2s_max, s); break;
@@ -567,7 +608,7 @@ void launch_move_t(int bin, const MoveArgs<C> &a, int grid, int log2s_max, hipSt
 
 int move_rows_per_block(int bin)
 {
-    static const int rows[NBINS] = {128, 32, 8, 4, 1, 1, 1};
+    static const int rows[NBINS] = {256, 64, 16, 4, 1, 1, 1};
     return rows[bin];
 }
 

@@ -118,7 +118,7 @@ enum Fam {
     F_COUNT
 };
 const char *FAM_NAMES[F_COUNT] = {
-    "move_bin0_2lanes", "move_bin1_8lanes", "move_bin2_32lanes", "move_bin3_wave",
+    "move_bin0_1lane", "move_bin1_4lanes", "move_bin2_16lanes", "move_bin3_wave",
     "move_bin4_block", "move_bin5_bigblock", "move_bin6_hub", "agg_bin0_8lanes",
     "agg_bin1_32lanes", "agg_bin2_wave", "agg_bin3_wave", "agg_bin4_block",
     "agg_bin5_bigblock", "agg_bin6_hub", "compact", "apply", "iteration_end", "level_setup",
