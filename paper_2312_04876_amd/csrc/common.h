@@ -59,6 +59,17 @@ constexpr int BIN_CHUNK = 4096;
 // Vertices per workgroup (and LDS table slots / 2) of the community counting kernels.
 constexpr int COMM_CHUNK = 2048;
 constexpr int COMM_LOG2S = 12;
+// Moves per workgroup step of the round-end apply kernel, and its LDS table
+// (2^APPLY_LOG2S slots >= twice the 2 * APPLY_CHUNK community keys).
+constexpr int APPLY_CHUNK = 512;
+constexpr int APPLY_LOG2S = 11;
+// Local-moving counters are accumulated per wavefront into NSPREAD rows of
+// SPREAD_W words (row = global wavefront id mod NSPREAD), so thousands of
+// wavefronts do not serialise on one address; the iteration-end kernel folds
+// the rows.  Row words: [0..1] 128-bit gain sum, then per degree bin b at
+// 2 + 4b: vertices, entries, distinct communities, moves.
+constexpr int NSPREAD = 64;
+constexpr int SPREAD_W = 32;
 
 __host__ __device__ inline int bin_of(int64_t d, int lds_max)
 {
@@ -110,6 +121,9 @@ struct DevScalars {
     unsigned long long s2[2];       // 128-bit sum of Sigma_c^2
     unsigned long long work[16][5]; // algorithmic work counters per kernel family
     int32_t pad[16];
+    // --- per-wavefront counter rows (folded and cleared by the iteration end);
+    // not copied back by the host's scalar reads ---
+    unsigned long long spread[NSPREAD][SPREAD_W];
 };
 
 // Work-counter slots (DevScalars::work[k]): move bins 0..NBINS-1

@@ -92,21 +92,67 @@ __device__ inline bool decide(const MoveArgs<C> &a, int dc, typename C::ST kv,
     return true;
 }
 
-template <class C, bool FAST>
-__device__ inline void commit(const MoveArgs<C> &a, int v, int dc, int bc, typename C::ST kv)
+// Fast mode applies a move at once: label, both community weights and both
+// sizes (HBM atomics), so every vertex decided later reads the new state.
+template <class C>
+__device__ inline void fast_apply(const MoveArgs<C> &a, int v, int dc, int bc, typename C::ST kv)
 {
     typedef typename C::ST ST;
+    a.Cp[v] = bc;
+    atomic_add_t<ST>(&a.Sig[dc], (ST)-kv);
+    atomic_add_t<ST>(&a.Sig[bc], kv);
+    atomicSub(&a.size[dc], 1);
+    atomicAdd(&a.size[bc], 1);
+}
+
+// Commits the moves decided by the lanes with m set (one lane per vertex);
+// every lane of the wavefront calls this.  Deterministic mode appends them to
+// the round's move list (one list reservation per wavefront), applied when
+// the round ends.
+template <class C, bool FAST>
+__device__ inline void record_moves(const MoveArgs<C> &a, bool m, int v, int dc, int bc,
+                                    typename C::ST kv)
+{
     if (FAST) {
-        a.Cp[v] = bc;
-        atomic_add_t<ST>(&a.Sig[dc], (ST)-kv);
-        atomic_add_t<ST>(&a.Sig[bc], kv);
-        atomicSub(&a.size[dc], 1);
-        atomicAdd(&a.size[bc], 1);
-    } else {
-        const int m = atomicAdd(a.mv_count, 1);
-        a.mv_v[m] = v;
-        a.mv_c[m] = bc;
+        if (m) fast_apply<C>(a, v, dc, bc, kv);
+        return;
     }
+    const unsigned long long b = __ballot(m);
+    if (b == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)b) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(a.mv_count, __popcll(b));
+    base = __shfl(base, leader, 64);
+    if (m) {
+        const int pos = base + __popcll(b & ((1ull << lane) - 1ull));
+        a.mv_v[pos] = v;
+        a.mv_c[pos] = bc;
+        a.mv_d[pos] = dc;
+    }
+}
+
+// The same for a single deciding thread.
+template <class C, bool FAST>
+__device__ inline void record_move(const MoveArgs<C> &a, int v, int dc, int bc,
+                                   typename C::ST kv)
+{
+    if (FAST) {
+        fast_apply<C>(a, v, dc, bc, kv);
+        return;
+    }
+    const int pos = atomicAdd(a.mv_count, 1);
+    a.mv_v[pos] = v;
+    a.mv_c[pos] = bc;
+    a.mv_d[pos] = dc;
+}
+
+// Counter row of the calling wavefront.
+template <class C>
+__device__ inline unsigned long long *counter_row(const MoveArgs<C> &a)
+{
+    const unsigned wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    return a.spread + (size_t)(wid & (NSPREAD - 1)) * SPREAD_W;
 }
 
 // Flush per-lane counters (all lanes of every wavefront call this).
@@ -121,17 +167,13 @@ __device__ inline void flush_counters(const MoveArgs<C> &a, typename C::SC gain,
     nk = wave_sum_u64(nk);
     nm = wave_sum_u64(nm);
     if ((threadIdx.x & 63) == 0) {
-        atomic_add_i128(a.sumN, g);
-        if (nv) atomicAdd(&a.work[0], nv);
-        if (ne) {
-            atomicAdd(&a.work[1], ne);
-            atomicAdd(a.it_scanned, ne);
-        }
-        if (nk) atomicAdd(&a.work[2], nk);
-        if (nm) {
-            atomicAdd(&a.work[3], nm);
-            atomicAdd(a.it_moves, nm);
-        }
+        unsigned long long *row = counter_row(a);
+        unsigned long long *col = row + 2 + 4 * a.bin;
+        if (g != 0) atomic_add_i128(row, g);
+        if (nv) atomicAdd(&col[0], nv);
+        if (ne) atomicAdd(&col[1], ne);
+        if (nk) atomicAdd(&col[2], nk);
+        if (nm) atomicAdd(&col[3], nm);
     }
 }
 
@@ -292,9 +334,9 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             if (mv) {
                 gain_acc += gain;
                 ++nm;
-                commit<C, FAST>(a, v, dc, bc, kv);
             }
         }
+        record_moves<C, FAST>(a, mv && gl == 0, v, dc, bc, kv);
         if (mv) {
 #pragma unroll
             for (int k = 0; k < E; ++k)
@@ -428,7 +470,7 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
             if (mv) {
                 gain_acc += gain;
                 ++nm;
-                commit<C, FAST>(a, v, dc, r.bc[0], kv);
+                record_move<C, FAST>(a, v, dc, r.bc[0], kv);
             }
         }
         __syncthreads();
@@ -487,10 +529,7 @@ __global__ __launch_bounds__(256) void k_move_hub_scatter(MoveArgs<C> a)
         if (k >= 0) hbm_insert<ST>(a.hkeys + t0, a.hvals + t0, T, k, s_vals[s]);
     }
     ne = wave_sum_u64(ne);
-    if ((threadIdx.x & 63) == 0 && ne) {
-        atomicAdd(&a.work[1], ne);
-        atomicAdd(a.it_scanned, ne);
-    }
+    if ((threadIdx.x & 63) == 0 && ne) atomicAdd(&counter_row(a)[2 + 4 * a.bin + 1], ne);
 }
 
 // Hubs, step 2: one workgroup per queued hub takes the argmax over its HBM
@@ -563,7 +602,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
             if (mv) {
                 gain_acc += gain;
                 ++nm;
-                commit<C, FAST>(a, v, dc, r.bc[0], kv);
+                record_move<C, FAST>(a, v, dc, r.bc[0], kv);
             }
         }
         __syncthreads();

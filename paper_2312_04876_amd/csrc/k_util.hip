@@ -447,25 +447,68 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a)
     }
 }
 
+// Slot of community c in the apply kernel's LDS table (inserted if absent).
+__device__ inline int apply_slot(int32_t *keys, int32_t c)
+{
+    constexpr uint32_t mask = (1u << APPLY_LOG2S) - 1u;
+    uint32_t h = hash32((uint32_t)c) >> (32 - APPLY_LOG2S);
+    for (;;) {
+        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == c) return (int)h;
+        if (k < 0) {
+            const int32_t old = atomicCAS(&keys[h], -1, c);
+            if (old < 0 || old == c) return (int)h;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
 template <typename ST>
 __global__ __launch_bounds__(256) void k_apply(const int32_t *mv_v, const int32_t *mv_c,
-                                               const int32_t *mv_count, int32_t *Cp, const ST *K,
-                                               ST *Sig, int32_t *size, int32_t cap,
-                                               const int32_t *done)
+                                               const int32_t *mv_d, const int32_t *mv_count,
+                                               int32_t *Cp, const ST *K, ST *Sig, int32_t *size,
+                                               int32_t cap, const int32_t *done)
 {
+    constexpr int S = 1 << APPLY_LOG2S;
+    __shared__ int32_t keys[S];
+    __shared__ ST dsig[S];
+    __shared__ int32_t dsz[S];
     if (*done) return;
     int m = *mv_count;
     if (m > cap) m = cap;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const int v = mv_v[k], c = mv_c[k];
-        const int d = Cp[v];
-        const ST kv = K[v];
-        Cp[v] = c;
-        atomic_add_t<ST>(&Sig[d], (ST)-kv);
-        atomic_add_t<ST>(&Sig[c], kv);
-        atomicSub(&size[d], 1);
-        atomicAdd(&size[c], 1);
+    if ((int64_t)blockIdx.x * APPLY_CHUNK >= m) return;
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        keys[s] = -1;
+        dsig[s] = 0;
+        dsz[s] = 0;
+    }
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * APPLY_CHUNK; base < m;
+         base += (int64_t)gridDim.x * APPLY_CHUNK) {
+        for (int q = threadIdx.x; q < APPLY_CHUNK; q += blockDim.x) {
+            const int64_t k = base + q;
+            if (k >= m) break;
+            const int v = mv_v[k], c = mv_c[k], d = mv_d[k];
+            const ST kv = K[v];
+            Cp[v] = c;
+            const int sd = apply_slot(keys, d);
+            atomic_add_t<ST>(&dsig[sd], (ST)-kv);
+            atomicSub(&dsz[sd], 1);
+            const int sc = apply_slot(keys, c);
+            atomic_add_t<ST>(&dsig[sc], kv);
+            atomicAdd(&dsz[sc], 1);
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < S; s += blockDim.x) {
+            const int32_t key = keys[s];
+            if (key < 0) continue;
+            if (dsig[s] != 0) atomic_add_t<ST>(&Sig[key], dsig[s]);
+            if (dsz[s] != 0) atomicAdd(&size[key], dsz[s]);
+            keys[s] = -1;
+            dsig[s] = 0;
+            dsz[s] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -480,11 +523,28 @@ __global__ void k_round_end(DevScalars *sc, int it)
     if (t == 0) sc->mv_count = 0;
 }
 
-__global__ void k_iter_end(DevScalars *sc, int it, double tau)
+__global__ __launch_bounds__(64) void k_iter_end(DevScalars *sc, int it, double tau)
 {
-    if (threadIdx.x != 0 || sc->done) return;
-    const i128 s = join_i128(sc->sumN[it][0], sc->sumN[it][1]);
-    const double dq = iteration_dq(s, sc->W);
+    if (sc->done) return;
+    const int lane = threadIdx.x;  // one counter row per lane
+    unsigned long long *row = sc->spread[lane];
+    const i128 g = wave_sum_i128(join_i128(row[0], row[1]));
+    unsigned long long moves = 0, scanned = 0;
+    for (int b = 0; b < NBINS; ++b) {
+        for (int k = 0; k < 4; ++k) {
+            const unsigned long long x = wave_sum_u64(row[2 + 4 * b + k]);
+            if (lane == 0) sc->work[WORK_MOVE + b][k] += x;
+            if (k == 1) scanned += x;
+            if (k == 3) moves += x;
+        }
+    }
+    for (int f = 0; f < SPREAD_W; ++f) row[f] = 0;
+    if (lane != 0) return;
+    sc->sumN[it][0] = (unsigned long long)g;
+    sc->sumN[it][1] = (unsigned long long)(g >> 64);
+    sc->moves[it] = moves;
+    sc->scanned[it] = scanned;
+    const double dq = iteration_dq(g, sc->W);
     sc->dq[it] = dq;
     sc->iters = it + 1;
     if (dq <= tau) sc->done = 1;
@@ -743,20 +803,21 @@ void launch_compact(const CompactArgs &a, hipStream_t s)
 }
 
 template <typename ST>
-void launch_apply(const int32_t *mv_v, const int32_t *mv_c, const int32_t *mv_count, int32_t *Cp,
-                  const ST *K, ST *Sig, int32_t *size, int32_t cap, const int32_t *done,
-                  hipStream_t s)
+void launch_apply(const int32_t *mv_v, const int32_t *mv_c, const int32_t *mv_d,
+                  const int32_t *mv_count, int32_t *Cp, const ST *K, ST *Sig, int32_t *size,
+                  int32_t cap, const int32_t *done, hipStream_t s)
 {
-    if (cap > 0)
-        k_apply<ST><<<grid_for(cap, 256, 2048), 256, 0, s>>>(mv_v, mv_c, mv_count, Cp, K, Sig,
-                                                             size, cap, done);
+    if (cap <= 0) return;
+    const int64_t chunks = ((int64_t)cap + APPLY_CHUNK - 1) / APPLY_CHUNK;
+    const int grid = (int)std::min<int64_t>(chunks, 2048);
+    k_apply<ST><<<grid, 256, 0, s>>>(mv_v, mv_c, mv_d, mv_count, Cp, K, Sig, size, cap, done);
 }
-template void launch_apply<int32_t>(const int32_t *, const int32_t *, const int32_t *, int32_t *,
-                                    const int32_t *, int32_t *, int32_t *, int32_t,
-                                    const int32_t *, hipStream_t);
-template void launch_apply<int64_t>(const int32_t *, const int32_t *, const int32_t *, int32_t *,
-                                    const int64_t *, int64_t *, int32_t *, int32_t,
-                                    const int32_t *, hipStream_t);
+template void launch_apply<int32_t>(const int32_t *, const int32_t *, const int32_t *,
+                                    const int32_t *, int32_t *, const int32_t *, int32_t *,
+                                    int32_t *, int32_t, const int32_t *, hipStream_t);
+template void launch_apply<int64_t>(const int32_t *, const int32_t *, const int32_t *,
+                                    const int32_t *, int32_t *, const int64_t *, int64_t *,
+                                    int32_t *, int32_t, const int32_t *, hipStream_t);
 
 void launch_round_end(DevScalars *sc, int it, hipStream_t s)
 {

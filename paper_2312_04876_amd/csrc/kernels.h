@@ -108,16 +108,16 @@ struct MoveArgs {
     typename C::ST *Sig;
     int32_t *size;
     uint8_t *flags_next;
-    int32_t *mv_v, *mv_c, *mv_count;   // deferred moves (deterministic mode)
+    int32_t *mv_v, *mv_c, *mv_d;       // deferred moves: vertex, new and old label
+    int32_t *mv_count;
     int32_t *hkeys;                    // HBM tables of the hub bin
     typename C::ST *hvals;
     const int64_t *hoff;               // table offset per hub
     const int32_t *hslice;             // first slice per hub (exclusive scan, nhubs + 1)
     uint8_t *hub_act;                  // hub queued in this round
     int32_t nhubs;
-    unsigned long long *sumN;          // 128-bit gain sum of this iteration
-    unsigned long long *work;          // [vertices, entries, keys, moves]
-    unsigned long long *it_moves, *it_scanned;
+    unsigned long long *spread;        // NSPREAD counter rows of SPREAD_W words
+    int32_t bin;                       // degree bin of this launch (counter columns)
     const int32_t *done;
     int64_t W;
     int32_t rule;                      // min-label rule for singleton moves
@@ -134,15 +134,20 @@ template <class C>
 void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t total_slices, int grid,
                       hipStream_t s);
 
-// Deferred moves of a round (deterministic mode).
+// Deferred moves of a round (deterministic mode): each mover relabelled, and
+// the community weights and sizes updated, each workgroup combining the
+// updates of APPLY_CHUNK moves per community in LDS before one HBM atomic per
+// community.
 template <typename ST>
-void launch_apply(const int32_t *mv_v, const int32_t *mv_c, const int32_t *mv_count, int32_t *Cp,
-                  const ST *K, ST *Sig, int32_t *size, int32_t cap, const int32_t *done,
-                  hipStream_t s);
+void launch_apply(const int32_t *mv_v, const int32_t *mv_c, const int32_t *mv_d,
+                  const int32_t *mv_count, int32_t *Cp, const ST *K, ST *Sig, int32_t *size,
+                  int32_t cap, const int32_t *done, hipStream_t s);
 
 // End of a round: processed += counts, counts = 0, mv_count = 0.
 void launch_round_end(DevScalars *sc, int it, hipStream_t s);
-// End of an iteration: delta-Q test against tau, done / iters update.
+// End of an iteration: folds the per-wavefront counter rows into the
+// iteration's gain sum, moves, scanned entries and the work counters, clears
+// them, then the delta-Q test against tau and the done / iters update.
 void launch_iter_end(DevScalars *sc, int it, double tau, hipStream_t s);
 
 // ----------------------------------------------------------------- aggregation

@@ -28,7 +28,7 @@ struct Layout {
     size_t total;
     int sb;  // bytes of K', Sigma', table values and aggregated weights (4 or 8)
     int64_t slots, scratch_elems;
-    size_t scalars, Cp, top, K, Sig, size, fa, fb, binorder, worklist, mv_v, mv_c;
+    size_t scalars, Cp, top, K, Sig, size, fa, fb, binorder, worklist, mv_v, mv_c, mv_d;
     size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hkeys, hvals, hsz, hoff, scratch;
@@ -62,6 +62,7 @@ Layout make_layout(int32_t n, int64_t nnz, int sb)
     L.worklist = take(4 * n1);
     L.mv_v = take(4 * n1);
     L.mv_c = take(4 * n1);
+    L.mv_d = take(4 * n1);
     L.used = take(4 * (n1 + 1));
     L.idmap = take(4 * (n1 + 1));
     L.ccount = take(4 * (n1 + 1));
@@ -146,7 +147,7 @@ struct louvain_ctx {
     DevScalars *hsc;  // pinned host copy
     int32_t *pinned_done;
     hipEvent_t it_ev[2];
-    int32_t *Cp, *top, *size, *binorder, *worklist, *mv_v, *mv_c;
+    int32_t *Cp, *top, *size, *binorder, *worklist, *mv_v, *mv_c, *mv_d;
     int32_t *used, *idmap, *ccount, *coff, *ctot, *cursor, *members, *cbinorder;
     uint8_t *fa, *fb;
     void *K, *Sig;
@@ -259,7 +260,8 @@ int sync_stream(louvain_ctx *ctx)
 
 int read_scalars(louvain_ctx *ctx)
 {
-    CK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->s));
+    CK(hipMemcpyAsync(ctx->hsc, ctx->sc, offsetof(DevScalars, spread), hipMemcpyDeviceToHost,
+                      ctx->s));
     return sync_stream(ctx);
 }
 
@@ -278,6 +280,8 @@ int setup_level(louvain_ctx *ctx)
     hipEvent_t ev;
     TRY(prof_begin(ctx, &ev));
     launch_fill_bytes_zero(ctx->sc, offsetof(DevScalars, err), s);
+    CKL();
+    launch_fill_bytes_zero(ctx->sc->spread, sizeof(ctx->sc->spread), s);
     CKL();
     launch_init_vertices(l.n, ctx->Cp, ctx->size, ctx->fa, ctx->fb, ctx->K, ctx->Sig, ctx->L.sb, s);
     launch_bin_count(l.n, l.off, l.deg, ctx->lds_max, ctx->bincnt, ctx->binoff, ctx->scratch,
@@ -351,6 +355,8 @@ int move_phase(louvain_ctx *ctx)
     a.size = ctx->size;
     a.mv_v = ctx->mv_v;
     a.mv_c = ctx->mv_c;
+    a.mv_d = ctx->mv_d;
+    a.spread = &ctx->sc->spread[0][0];
     a.mv_count = &ctx->sc->mv_count;
     a.hkeys = ctx->hkeys;
     a.hvals = (ST *)ctx->hvals;
@@ -375,9 +381,6 @@ int move_phase(louvain_ctx *ctx)
         uint8_t *cur = (it & 1) ? ctx->fb : ctx->fa;
         uint8_t *nxt = (it & 1) ? ctx->fa : ctx->fb;
         a.flags_next = nxt;
-        a.sumN = ctx->sc->sumN[it];
-        a.it_moves = &ctx->sc->moves[it];
-        a.it_scanned = &ctx->sc->scanned[it];
         for (int r = 0; r < rounds; ++r) {
             CompactArgs ca;
             ca.binorder = ctx->binorder;
@@ -403,7 +406,7 @@ int move_phase(louvain_ctx *ctx)
                 if (grid[b] <= 0) continue;
                 a.list_begin = ctx->bins.start[b];
                 a.count = &ctx->sc->bin_count[b];
-                a.work = ctx->sc->work[WORK_MOVE + b];
+                a.bin = b;
                 TRY(prof_begin(ctx, &ev));
                 if (b < NBINS - 1)
                     launch_move<C>(b, fast, a, grid[b], log2s[b], s);
@@ -414,8 +417,9 @@ int move_phase(louvain_ctx *ctx)
             }
             TRY(prof_begin(ctx, &ev));
             if (!fast) {
-                launch_apply<ST>(ctx->mv_v, ctx->mv_c, &ctx->sc->mv_count, ctx->Cp, (const ST *)ctx->K,
-                                 (ST *)ctx->Sig, ctx->size, ctx->nb, &ctx->sc->done, s);
+                launch_apply<ST>(ctx->mv_v, ctx->mv_c, ctx->mv_d, &ctx->sc->mv_count, ctx->Cp,
+                                 (const ST *)ctx->K, (ST *)ctx->Sig, ctx->size, ctx->nb,
+                                 &ctx->sc->done, s);
                 CKL();
             }
             launch_round_end(ctx->sc, it, s);
@@ -832,6 +836,7 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     ctx->worklist = (int32_t *)(b + L.worklist);
     ctx->mv_v = (int32_t *)(b + L.mv_v);
     ctx->mv_c = (int32_t *)(b + L.mv_c);
+    ctx->mv_d = (int32_t *)(b + L.mv_d);
     ctx->used = (int32_t *)(b + L.used);
     ctx->idmap = (int32_t *)(b + L.idmap);
     ctx->ccount = (int32_t *)(b + L.ccount);
