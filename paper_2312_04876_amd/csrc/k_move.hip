@@ -147,6 +147,47 @@ __device__ inline void record_move(const MoveArgs<C> &a, int v, int dc, int bc,
     a.mv_d[pos] = dc;
 }
 
+// Fast mode, bins 0-3: a workgroup adds the community weight and size changes
+// of its moves into an LDS table and applies them with one HBM atomic per
+// community every few steps.  A GPU decides thousands of vertices against
+// the same state anyway, so this adds little delay, while it folds the many
+// moves into one popular community (atomics performed at the memory side,
+// each also evicting the line every scoring lane reads) into a few.
+template <typename ST>
+__device__ inline void pending_add(int32_t *keys, ST *dsig, int32_t *dsz, int log2s, int32_t c,
+                                   ST dk, int ds)
+{
+    const uint32_t mask = (1u << log2s) - 1u;
+    uint32_t h = hash32((uint32_t)c) >> (32 - log2s);
+    for (;;) {
+        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == c) break;
+        if (k < 0) {
+            const int32_t old = atomicCAS(&keys[h], -1, c);
+            if (old < 0 || old == c) break;
+        }
+        h = (h + 1) & mask;
+    }
+    atomic_add_t<ST>(&dsig[h], dk);
+    atomicAdd(&dsz[h], ds);
+}
+
+template <class C>
+__device__ inline void pending_flush(const MoveArgs<C> &a, int32_t *keys, typename C::ST *dsig,
+                                     int32_t *dsz, int slots)
+{
+    typedef typename C::ST ST;
+    for (int q = threadIdx.x; q < slots; q += blockDim.x) {
+        const int32_t c = keys[q];
+        if (c < 0) continue;
+        if (dsig[q] != 0) atomic_add_t<ST>(&a.Sig[c], dsig[q]);
+        if (dsz[q] != 0) atomicAdd(&a.size[c], dsz[q]);
+        keys[q] = -1;
+        dsig[q] = 0;
+        dsz[q] = 0;
+    }
+}
+
 // Counter row of the calling wavefront.
 template <class C>
 __device__ inline unsigned long long *counter_row(const MoveArgs<C> &a)
@@ -198,10 +239,10 @@ __device__ inline void consider(const MoveArgs<C> &a, int dc, typename C::ST kv,
 }
 
 // Insert (c, w) into a power-of-two LDS table; returns the slot, and sets
-// *fresh when c was a new key.
+// *own when this call created the key.
 template <typename ST>
 __device__ inline int lds_insert_slot(int32_t *keys, ST *vals, int log2s, int32_t c, ST w,
-                                      int *fresh)
+                                      bool *own)
 {
     const uint32_t mask = (1u << log2s) - 1u;
     uint32_t h = hash32((uint32_t)c) >> (32 - log2s);
@@ -209,13 +250,14 @@ __device__ inline int lds_insert_slot(int32_t *keys, ST *vals, int log2s, int32_
         const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (k == c) {
             atomic_add_t<ST>(&vals[h], w);
+            *own = false;
             return (int)h;
         }
         if (k < 0) {
             const int32_t old = atomicCAS(&keys[h], -1, c);
             if (old < 0 || old == c) {
                 atomic_add_t<ST>(&vals[h], w);
-                *fresh += old < 0 ? 1 : 0;
+                *own = old < 0;
                 return (int)h;
             }
         }
@@ -225,9 +267,9 @@ __device__ inline int lds_insert_slot(int32_t *keys, ST *vals, int log2s, int32_
 
 // Bins 0-3: G lanes per vertex (64/G vertices per wavefront), lane l holding
 // entries l, l+G, ... (up to E of them), LDS table of 2^LOG2S slots per group
-// (groups padded by one slot to spread LDS banks).  Each lane scores the
-// communities of its own entries from the slots it inserted into, so the
-// table is never scanned; duplicates score the same candidate twice.
+// (groups padded by one slot to spread LDS banks).  The lane whose insert
+// created a community's slot scores that community (one read of its total
+// per distinct community), so the table is never scanned.
 template <class C, int G, int E, int LOG2S, bool FAST>
 __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
 {
@@ -237,8 +279,16 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
     constexpr int SP = S + 1;  // padded group stride
     constexpr int GPW = 64 / G;
     constexpr int NG = 4 * GPW;
+    // fast mode: community updates pending in LDS, flushed every FL steps
+    constexpr int FL = NG >= 64 ? 1 : 64 / NG;
+    constexpr int PLOG2 = NG * FL >= 256 ? 10 : 8;  // >= 4 slots per decided vertex
+    constexpr int PS = FAST ? 1 << PLOG2 : 1;
+    static_assert(!FAST || PS >= 4 * NG * FL, "pending table too small");
     __shared__ ST s_vals[NG * SP];
     __shared__ int32_t s_keys[NG * SP];
+    __shared__ int32_t p_keys[PS];
+    __shared__ ST p_sig[PS];
+    __shared__ int32_t p_sz[PS];
     if (*a.done) return;
     const int count = *a.count;
     if (count == 0) return;
@@ -250,11 +300,19 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
         keys[q] = -1;
         vals[q] = 0;
     }
-    wave_sync();
+    if (FAST)
+        for (int q = threadIdx.x; q < PS; q += 256) {
+            p_keys[q] = -1;
+            p_sig[q] = 0;
+            p_sz[q] = 0;
+        }
+    __syncthreads();
     SC gain_acc = 0;
     unsigned long long nv = 0, ne = 0, nk = 0, nm = 0;
     const int stride = gridDim.x * NG;
-    for (int base = (blockIdx.x * 4 + wave) * GPW; base < count; base += stride) {
+    int step = 0;
+    for (int b0 = blockIdx.x * NG; b0 < count; b0 += stride, ++step) {
+        const int base = b0 + wave * GPW;
         const int idx = base + grp;
         const bool has = idx < count;
         const int v = has ? a.worklist[a.list_begin + idx] : 0;
@@ -267,6 +325,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             kv = a.K[v];
         }
         int j[E], c[E], slot[E];
+        bool own[E];
         ST w[E];
 #pragma unroll
         for (int k = 0; k < E; ++k) {
@@ -276,29 +335,30 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
         }
 #pragma unroll
         for (int k = 0; k < E; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
-        int nonself = 0, fresh = 0;
+        int nonself = 0;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             ne += j[k] >= 0 ? 1 : 0;
             slot[k] = -1;
+            own[k] = false;
             if (c[k] >= 0) {
                 ++nonself;
-                slot[k] = lds_insert_slot<ST>(keys, vals, LOG2S, c[k], w[k], &fresh);
+                slot[k] = lds_insert_slot<ST>(keys, vals, LOG2S, c[k], w[k], &own[k]);
+                nk += own[k] ? 1 : 0;
             }
         }
-        nk += fresh;
         wave_sync();
         ST x[E], sg[E];
 #pragma unroll
-        for (int k = 0; k < E; ++k) x[k] = slot[k] >= 0 ? vals[slot[k]] : (ST)0;
+        for (int k = 0; k < E; ++k) x[k] = own[k] ? vals[slot[k]] : (ST)0;
 #pragma unroll
-        for (int k = 0; k < E; ++k) sg[k] = (c[k] >= 0 && c[k] != dc) ? a.Sig[c[k]] : (ST)0;
+        for (int k = 0; k < E; ++k) sg[k] = (own[k] && c[k] != dc) ? a.Sig[c[k]] : (ST)0;
         SC best = score_min<SC>();
         int bc = INT_MAX;
         ST hd = 0;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-            if (c[k] < 0) continue;
+            if (!own[k]) continue;
             if (c[k] == dc) {
                 hd = x[k];
             } else {
@@ -312,7 +372,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
         wave_sync();
 #pragma unroll
         for (int k = 0; k < E; ++k)
-            if (slot[k] >= 0) {
+            if (own[k]) {
                 keys[slot[k]] = -1;
                 vals[slot[k]] = 0;
             }
@@ -336,11 +396,24 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
                 ++nm;
             }
         }
-        record_moves<C, FAST>(a, mv && gl == 0, v, dc, bc, kv);
         if (mv) {
 #pragma unroll
             for (int k = 0; k < E; ++k)
                 if (j[k] >= 0) a.flags_next[j[k]] = 1;
+        }
+        if (FAST) {
+            if (mv && gl == 0) {
+                a.Cp[v] = bc;
+                pending_add<ST>(p_keys, p_sig, p_sz, PLOG2, dc, (ST)-kv, -1);
+                pending_add<ST>(p_keys, p_sig, p_sz, PLOG2, bc, kv, 1);
+            }
+            if (step % FL == FL - 1 || b0 + stride >= count) {  // uniform over the block
+                __syncthreads();
+                pending_flush<C>(a, p_keys, p_sig, p_sz, PS);
+                __syncthreads();
+            }
+        } else {
+            record_moves<C, FAST>(a, mv && gl == 0, v, dc, bc, kv);
         }
         wave_sync();
     }
