@@ -115,7 +115,7 @@ struct DevScalars {
     int32_t pad1;
     unsigned long long scan_total;
     unsigned long long hub_slices;   // row slices of the hub bin (sum over hubs)
-    unsigned long long hub_tslices;  // table slices of the hub bin (aggregation)
+    unsigned long long hub_tslices;  // table slices of the hub bin
     unsigned long long W;
     unsigned long long sigma;       // sum of intra-community entries
     unsigned long long s2[2];       // 128-bit sum of Sigma_c^2

@@ -605,9 +605,70 @@ __global__ __launch_bounds__(256) void k_move_hub_scatter(MoveArgs<C> a)
     if ((threadIdx.x & 63) == 0 && ne) atomicAdd(&counter_row(a)[2 + 4 * a.bin + 1], ne);
 }
 
-// Hubs, step 2: one workgroup per queued hub takes the argmax over its HBM
-// table, moves, and clears the slots it read so the table is empty again for
-// the next user.
+// Hubs, step 2: one workgroup per HUB_SLICE-slot slice of a queued hub's HBM
+// table scores the communities in it, clears their slots (the table is empty
+// again for the next user) and leaves the slice's best candidate in hpart.
+template <class C>
+__global__ __launch_bounds__(256) void k_move_hub_part(MoveArgs<C> a)
+{
+    typedef typename C::ST ST;
+    typedef typename C::SC SC;
+    constexpr int Q = HUB_SLICE / 256;
+    __shared__ BlockRed<SC, ST, 4> r;
+    if (*a.done) return;
+    const int h = owner_slice(a.htslice, a.nhubs, (int)blockIdx.x);
+    if (!a.hub_act[h]) return;
+    const int v = a.binorder[a.list_begin + h];
+    const int d = row_len(a.off, a.deg, v);
+    const int64_t t0 = a.hoff[h];
+    const uint32_t T = (uint32_t)hub_slots(d);
+    const uint32_t s0 = (uint32_t)((int)blockIdx.x - a.htslice[h]) * HUB_SLICE;
+    int32_t *keys = a.hkeys + t0;
+    ST *vals = a.hvals + t0;
+    const int dc = a.Cp[v];
+    const ST kv = a.K[v];
+    int kk[Q];
+    ST xx[Q], sg[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t s = s0 + threadIdx.x + q * 256;
+        kk[q] = s < T ? __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t s = s0 + threadIdx.x + q * 256;
+        xx[q] = kk[q] >= 0 ? __hip_atomic_load(&vals[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : (ST)0;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
+    SC best = score_min<SC>();
+    int bc = INT_MAX;
+    ST hd = 0;
+    int nk = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (kk[q] >= 0) {
+            const uint32_t s = s0 + threadIdx.x + q * 256;
+            keys[s] = -1;
+            vals[s] = 0;
+            ++nk;
+        }
+        consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+    }
+    block_reduce<SC, ST, 4>(r, best, bc, hd, nk);
+    if (threadIdx.x == 0) {
+        HubPart<C> p;
+        p.best = r.best[0];
+        p.bc = r.bc[0];
+        p.hd = r.hd[0];
+        p.nk = r.nonself[0];
+        ((HubPart<C> *)a.hpart)[blockIdx.x] = p;
+    }
+}
+
+// Hubs, step 3: one workgroup per queued hub takes the argmax over its table
+// slices and moves.
 template <class C, bool FAST>
 __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
 {
@@ -617,6 +678,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
     __shared__ BlockRed<SC, ST, NW> r;
     if (*a.done) return;
     const int count = *a.count;
+    const HubPart<C> *part = (const HubPart<C> *)a.hpart;
     SC gain_acc = 0;
     unsigned long long nv = 0, nk = 0, nm = 0;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
@@ -625,51 +687,30 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
         const int v = a.binorder[p];
         const int beg = a.off[v];
         const int d = row_len(a.off, a.deg, v);
-        const int64_t t0 = a.hoff[h];
-        const uint32_t T = (uint32_t)hub_slots(d);
-        int32_t *keys = a.hkeys + t0;
-        ST *vals = a.hvals + t0;
-        // a hub row holds more than the LDS row limit of distinct targets, so it
-        // always has an entry other than a self-loop
-        const int nonself = threadIdx.x == 0 ? 1 : 0;
-        if (threadIdx.x == 0) a.hub_act[h] = 0;
+        const int q1 = h + 1 < a.nhubs ? a.htslice[h + 1] : (int)*a.htslices;
         const int dc = a.Cp[v];
         const ST kv = a.K[v];
         SC best = score_min<SC>();
         int bc = INT_MAX;
         ST hd = 0;
-        for (uint32_t s0 = threadIdx.x; s0 < T; s0 += 4 * HUB_THREADS) {
-            int kk[4];
-            ST xx[4], sg[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t s = s0 + q * HUB_THREADS;
-                kk[q] = s < T ? __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                              : -1;
+        int keys = 0;
+        for (int q = a.htslice[h] + threadIdx.x; q < q1; q += HUB_THREADS) {
+            const HubPart<C> pp = part[q];
+            if (better(pp.best, pp.bc, best, bc)) {
+                best = pp.best;
+                bc = pp.bc;
             }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t s = s0 + q * HUB_THREADS;
-                xx[q] = kk[q] >= 0 ? __hip_atomic_load(&vals[s], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT)
-                                   : (ST)0;
-                sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (kk[q] >= 0) {
-                    const uint32_t s = s0 + q * HUB_THREADS;
-                    keys[s] = -1;
-                    vals[s] = 0;
-                    ++nk;
-                }
-                consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
-            }
+            hd += pp.hd;
+            keys += pp.nk;
         }
-        block_reduce<SC, ST, NW>(r, best, bc, hd, nonself);
+        block_reduce<SC, ST, NW>(r, best, bc, hd, keys);
         if (threadIdx.x == 0) {
+            a.hub_act[h] = 0;
+            nk += (unsigned long long)r.nonself[0];
+            // a hub row holds more than the LDS row limit of distinct targets, so
+            // it always has an entry other than a self-loop
             SC gain = 0;
-            const bool mv = decide<C>(a, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0], &gain);
+            const bool mv = decide<C>(a, dc, kv, r.best[0], r.bc[0], r.hd[0], 1, &gain);
             r.move = mv ? 1 : 0;
             ++nv;
             if (mv) {
@@ -681,7 +722,6 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
         __syncthreads();
         if (r.move)
             for (int e = threadIdx.x; e < d; e += HUB_THREADS) a.flags_next[a.tgt[beg + e]] = 1;
-        __threadfence();
         __syncthreads();
     }
     flush_counters<C>(a, gain_acc, nv, 0, nk, nm);
@@ -741,21 +781,22 @@ template void launch_move<CfgWideIn>(int, bool, const MoveArgs<CfgWideIn> &, int
 template void launch_move<CfgWide>(int, bool, const MoveArgs<CfgWide> &, int, int, hipStream_t);
 
 template <class C>
-void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t total_slices, int grid,
-                      hipStream_t s)
+void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t total_slices,
+                      int32_t table_slices, int grid, hipStream_t s)
 {
-    if (total_slices <= 0 || grid <= 0) return;
+    if (total_slices <= 0 || table_slices <= 0 || grid <= 0) return;
     k_move_hub_scatter<C><<<total_slices, 256, 0, s>>>(a);
+    k_move_hub_part<C><<<table_slices, 256, 0, s>>>(a);
     if (fast)
         k_move_hub<C, true><<<grid, HUB_THREADS, 0, s>>>(a);
     else
         k_move_hub<C, false><<<grid, HUB_THREADS, 0, s>>>(a);
 }
-template void launch_move_hubs<CfgNarrow>(bool, const MoveArgs<CfgNarrow> &, int32_t, int,
-                                          hipStream_t);
-template void launch_move_hubs<CfgWideIn>(bool, const MoveArgs<CfgWideIn> &, int32_t, int,
-                                          hipStream_t);
-template void launch_move_hubs<CfgWide>(bool, const MoveArgs<CfgWide> &, int32_t, int,
+template void launch_move_hubs<CfgNarrow>(bool, const MoveArgs<CfgNarrow> &, int32_t, int32_t,
+                                          int, hipStream_t);
+template void launch_move_hubs<CfgWideIn>(bool, const MoveArgs<CfgWideIn> &, int32_t, int32_t,
+                                          int, hipStream_t);
+template void launch_move_hubs<CfgWide>(bool, const MoveArgs<CfgWide> &, int32_t, int32_t, int,
                                         hipStream_t);
 
 }  // namespace lv

@@ -96,6 +96,15 @@ struct CompactArgs {
 };
 void launch_compact(const CompactArgs &a, hipStream_t s);
 
+// Best candidate of one HUB_SLICE-slot slice of a hub's HBM table.
+template <class C>
+struct HubPart {
+    typename C::SC best;
+    typename C::ST hd;   // weight to the own community, if its key is in the slice
+    int32_t bc;
+    int32_t nk;          // keys in the slice
+};
+
 template <class C>
 struct MoveArgs {
     const int32_t *off, *deg, *tgt;
@@ -113,7 +122,10 @@ struct MoveArgs {
     int32_t *hkeys;                    // HBM tables of the hub bin
     typename C::ST *hvals;
     const int64_t *hoff;               // table offset per hub
-    const int32_t *hslice;             // first slice per hub (exclusive scan, nhubs + 1)
+    const int32_t *hslice;             // first row slice per hub (exclusive scan)
+    const int32_t *htslice;            // first table slice per hub (exclusive scan)
+    const unsigned long long *htslices;  // total table slices
+    void *hpart;                       // HubPart<C> per table slice
     uint8_t *hub_act;                  // hub queued in this round
     int32_t nhubs;
     unsigned long long *spread;        // NSPREAD counter rows of SPREAD_W words
@@ -129,10 +141,11 @@ void launch_move(int bin, bool fast, const MoveArgs<C> &a, int grid, int log2s_m
                  hipStream_t s);
 int move_rows_per_block(int bin);
 // Hub bin: one workgroup per row slice (all hubs' slices, inactive ones exit),
-// then one workgroup per queued hub for the argmax and the move.
+// one per table slice for the slice's best candidate, then one workgroup per
+// queued hub for the argmax over its slices and the move.
 template <class C>
-void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t total_slices, int grid,
-                      hipStream_t s);
+void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t total_slices,
+                      int32_t table_slices, int grid, hipStream_t s);
 
 // Deferred moves of a round (deterministic mode): each mover relabelled, and
 // the community weights and sizes updated, each workgroup combining the

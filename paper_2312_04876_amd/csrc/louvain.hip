@@ -32,7 +32,7 @@ struct Layout {
     size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hkeys, hvals, hsz, hoff, scratch;
-    size_t bincnt, binoff, slA, slB, mpre, hub_act;
+    size_t bincnt, binoff, slA, slB, mpre, hub_act, hpart;
 };
 
 Layout make_layout(int32_t n, int64_t nnz, int sb)
@@ -91,6 +91,8 @@ Layout make_layout(int32_t n, int64_t nnz, int sb)
     L.slB = take(4 * (n1 + 1));
     L.mpre = take(4 * (n1 + 1));
     L.hub_act = take(n1);
+    // per hub table slice (HUB_SLICE slots of a table of about 2 slots per entry)
+    L.hpart = take(32 * ((size_t)z / 512 + 64));
     L.total = cur;
     return L;
 }
@@ -157,8 +159,10 @@ struct louvain_ctx {
     void *hvals;
     int64_t *hsz, *hoff, *scratch;
     int32_t *bincnt, *binoff, *slA, *slB, *mpre;
+    void *hpart;
     uint8_t *hub_act;
     int32_t hub_slices;  // row slices of the current level's hubs
+    int32_t hub_tslices; // table slices of the current level's hubs
     int64_t W;
     bool wide;
     int32_t lds_max;     // LDS row limit of the bins (LDS_MAX_NARROW or LDS_MAX_WIDE)
@@ -297,13 +301,17 @@ int setup_level(louvain_ctx *ctx)
     CKL();
     const int hubs = bins_of(ctx, NBINS - 1);
     ctx->hub_slices = 0;
+    ctx->hub_tslices = 0;
     if (hubs > 0) {
-        // HBM table offsets and row slices of the hubs (cursor is free during moving)
+        // HBM table offsets, row slices and table slices of the hubs (cursor and
+        // ccount are free during moving)
         launch_hub_sizes(ctx->binorder, ctx->bins.start[NBINS - 1], ctx->bins.start[NBINS], l.off,
-                         l.deg, INT64_MAX, ctx->hsz, ctx->cursor, nullptr, s);
+                         l.deg, INT64_MAX, ctx->hsz, ctx->cursor, ctx->ccount, s);
         launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
         launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->slA, hubs, ctx->scratch,
                                                 &ctx->sc->hub_slices, s);
+        launch_exclusive_scan<int32_t, int32_t>(ctx->ccount, ctx->slB, hubs, ctx->scratch,
+                                                &ctx->sc->hub_tslices, s);
         launch_fill_u8(ctx->hub_act, 0, hubs, s);
         CKL();
     }
@@ -327,6 +335,7 @@ int setup_level(louvain_ctx *ctx)
     if (hubs > 0) {
         TRY(read_scalars(ctx));
         ctx->hub_slices = (int32_t)ctx->hsc->hub_slices;
+        ctx->hub_tslices = (int32_t)ctx->hsc->hub_tslices;
     }
     return LOUVAIN_OK;
 }
@@ -362,6 +371,9 @@ int move_phase(louvain_ctx *ctx)
     a.hvals = (ST *)ctx->hvals;
     a.hoff = ctx->hoff;
     a.hslice = ctx->slA;
+    a.htslice = ctx->slB;
+    a.htslices = &ctx->sc->hub_tslices;
+    a.hpart = ctx->hpart;
     a.hub_act = ctx->hub_act;
     a.nhubs = bins_of(ctx, NBINS - 1);
     a.done = &ctx->sc->done;
@@ -411,7 +423,7 @@ int move_phase(louvain_ctx *ctx)
                 if (b < NBINS - 1)
                     launch_move<C>(b, fast, a, grid[b], log2s[b], s);
                 else
-                    launch_move_hubs<C>(fast, a, ctx->hub_slices, grid[b], s);
+                    launch_move_hubs<C>(fast, a, ctx->hub_slices, ctx->hub_tslices, grid[b], s);
                 CKL();
                 TRY(prof_end(ctx, F_MOVE0 + b, ev));
             }
@@ -862,6 +874,7 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     ctx->binoff = (int32_t *)(b + L.binoff);
     ctx->slA = (int32_t *)(b + L.slA);
     ctx->slB = (int32_t *)(b + L.slB);
+    ctx->hpart = (void *)(b + L.hpart);
     ctx->mpre = (int32_t *)(b + L.mpre);
     ctx->hub_act = b + L.hub_act;
     // the scalar block keeps W; the hash slab starts empty and every user clears what it used
