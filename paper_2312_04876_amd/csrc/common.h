@@ -54,6 +54,26 @@ constexpr int BLOCK_THREADS = 512;
 // communities are combined in LDS before they reach HBM atomics.
 constexpr int HUB_SLICE = 2048;
 constexpr int HUB_LOG2S = 12;
+// Hub rows in local moving are not put in HBM hashtables: each round, the
+// (community, weight) pairs of a queued hub's row are counting-sorted into
+// partitions by a hash of the community, and one workgroup per partition
+// folds it in an LDS table of 2^hub_plog2 slots.  Partitions hold about a
+// quarter of that many pairs (so about a quarter of the slots are used), at
+// most HUB_MAXP per hub; a workgroup of the sorting kernels handles
+// HUB_PSLICE entries of a row.
+constexpr int HUB_PSLICE = 8192;
+constexpr int HUB_MAXP = 1024;
+template <typename ST>
+__host__ __device__ constexpr int hub_plog2() { return 12; }
+template <typename ST>
+__host__ __device__ constexpr int hub_part_pairs() { return 1 << (hub_plog2<ST>() - 2); }
+// Partitions of a hub row of d entries.
+template <typename ST>
+__host__ __device__ inline int hub_parts(int64_t d)
+{
+    const int64_t p = (d + hub_part_pairs<ST>() - 1) / hub_part_pairs<ST>();
+    return (int)(p < 1 ? 1 : (p > HUB_MAXP ? HUB_MAXP : p));
+}
 // Rows per workgroup of the binning and compaction kernels.
 constexpr int BIN_CHUNK = 4096;
 // Vertices per workgroup (and LDS table slots / 2) of the community counting kernels.
@@ -136,6 +156,22 @@ constexpr int WORK_AGG = NBINS;
 // Device helpers.
 
 __device__ inline uint32_t hash32(uint32_t k) { return k * 2654435761u; }
+
+// A second, independent bijective mix of 32-bit keys (the MurmurHash3
+// finaliser); its high bits pick a hub row's partition.
+__device__ inline uint32_t mix32(uint32_t k)
+{
+    k ^= k >> 16;
+    k *= 0x85ebca6bu;
+    k ^= k >> 13;
+    k *= 0xc2b2ae35u;
+    k ^= k >> 16;
+    return k;
+}
+__device__ inline int part_of(int32_t c, int parts)
+{
+    return (int)(((uint64_t)mix32((uint32_t)c) * (uint64_t)parts) >> 32);
+}
 
 // Exact 128-bit accumulation into a two-word (lo, hi) counter: the carry out
 // of the low word of this addition goes into the high word, so the total is

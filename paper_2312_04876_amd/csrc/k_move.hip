@@ -45,29 +45,6 @@ __device__ inline int lds_insert(int32_t *keys, ST *vals, int log2s, int32_t c, 
     }
 }
 
-// Insert into an HBM table of T slots (T >= 2 * row length); index by the
-// high half of hash * T.
-template <typename ST>
-__device__ inline void hbm_insert(int32_t *keys, ST *vals, uint32_t T, int32_t c, ST w)
-{
-    uint32_t h = (uint32_t)(((uint64_t)hash32((uint32_t)c) * (uint64_t)T) >> 32);
-    for (;;) {
-        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (k == c) {
-            atomic_add_t<ST>(&vals[h], w);
-            return;
-        }
-        if (k < 0) {
-            const int32_t old = atomicCAS(&keys[h], -1, c);
-            if (old < 0 || old == c) {
-                atomic_add_t<ST>(&vals[h], w);
-                return;
-            }
-        }
-        h = (h + 1 == T) ? 0u : h + 1;
-    }
-}
-
 // Candidate order: higher score first, then lower community id.
 template <typename SC>
 __device__ inline bool better(SC s, int c, SC bs, int bc)
@@ -554,107 +531,245 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
     flush_counters<C>(a, gain_acc, nv, ne, nk, nm);
 }
 
-// Hubs, step 1: one workgroup per HUB_SLICE-entry slice of a queued hub's row
-// folds the slice into an LDS table, then adds the table into the hub's HBM
-// table (hkeys/hvals + hoff[hub]).
+// Sorting slice k of the hub bin: hub h, entries [e0, e1) of its row.
 template <class C>
-__global__ __launch_bounds__(256) void k_move_hub_scatter(MoveArgs<C> a)
+__device__ inline bool hub_slice(const MoveArgs<C> &a, int k, int *h, int *v, int *beg, int *e0,
+                                 int *e1, int *parts, int *gp0)
 {
-    typedef typename C::ST ST;
-    constexpr int S = 1 << HUB_LOG2S;
-    constexpr int E = HUB_SLICE / 256;
-    __shared__ ST s_vals[S];
-    __shared__ int32_t s_keys[S];
+    *h = owner_slice(a.hslice, a.nhubs, k);
+    if (!a.hub_act[*h]) return false;
+    *v = a.binorder[a.list_begin + *h];
+    *beg = a.off[*v];
+    const int d = row_len(a.off, a.deg, *v);
+    *e0 = (k - a.hslice[*h]) * HUB_PSLICE;
+    *e1 = min(*e0 + HUB_PSLICE, d);
+    *gp0 = a.htslice[*h];
+    *parts = (*h + 1 < a.nhubs ? a.htslice[*h + 1] : (int)*a.htslices) - *gp0;
+    return true;
+}
+
+// Hubs, step 1: one workgroup per HUB_PSLICE entries of a queued hub's row
+// stages the community of every entry (-1 for a self-loop) and adds the
+// slice's pair count per partition into pcount.
+template <class C>
+__global__ __launch_bounds__(256) void k_hub_count(MoveArgs<C> a)
+{
+    __shared__ int32_t hist[HUB_MAXP];
     if (*a.done) return;
-    const int h = owner_slice(a.hslice, a.nhubs, (int)blockIdx.x);
-    if (!a.hub_act[h]) return;
-    const int v = a.binorder[a.list_begin + h];
-    const int beg = a.off[v];
-    const int d = row_len(a.off, a.deg, v);
-    const int e0 = ((int)blockIdx.x - a.hslice[h]) * HUB_SLICE;
-    for (int s = threadIdx.x; s < S; s += 256) {
-        s_keys[s] = -1;
-        s_vals[s] = 0;
-    }
-    int j[E], c[E];
-    ST w[E];
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-        const int e = e0 + (int)threadIdx.x + k * 256;
-        j[k] = e < d ? a.tgt[beg + e] : -1;
-    }
-#pragma unroll
-    for (int k = 0; k < E; ++k) w[k] = j[k] >= 0 ? (ST)a.w[beg + e0 + (int)threadIdx.x + k * 256] : (ST)0;
-#pragma unroll
-    for (int k = 0; k < E; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
+    int h, v, beg, e0, e1, parts, gp0;
+    if (!hub_slice(a, (int)blockIdx.x, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
+    for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
     __syncthreads();
+    int32_t *stage = a.hstage + a.hoff[h];
     unsigned long long ne = 0;
+    for (int c0 = e0; c0 < e1; c0 += 256 * 8) {
+        int j[8], c[8];
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-        ne += j[k] >= 0 ? 1 : 0;
-        if (c[k] >= 0) lds_insert<ST>(s_keys, s_vals, HUB_LOG2S, c[k], w[k]);
+        for (int k = 0; k < 8; ++k) {
+            const int e = c0 + (int)threadIdx.x + k * 256;
+            j[k] = e < e1 ? a.tgt[beg + e] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = c0 + (int)threadIdx.x + k * 256;
+            if (j[k] < 0) continue;
+            ++ne;
+            stage[e] = c[k];
+            if (c[k] >= 0) atomicAdd(&hist[part_of(c[k], parts)], 1);
+        }
     }
     __syncthreads();
-    const int64_t t0 = a.hoff[h];
-    const uint32_t T = (uint32_t)hub_slots(d);
-    for (int s = threadIdx.x; s < S; s += 256) {
-        const int k = s_keys[s];
-        if (k >= 0) hbm_insert<ST>(a.hkeys + t0, a.hvals + t0, T, k, s_vals[s]);
-    }
+    for (int p = threadIdx.x; p < parts; p += 256)
+        if (hist[p]) atomicAdd(&a.pcount[gp0 + p], hist[p]);
     ne = wave_sum_u64(ne);
     if ((threadIdx.x & 63) == 0 && ne) atomicAdd(&counter_row(a)[2 + 4 * a.bin + 1], ne);
 }
 
-// Hubs, step 2: one workgroup per HUB_SLICE-slot slice of a queued hub's HBM
-// table scores the communities in it, clears their slots (the table is empty
-// again for the next user) and leaves the slice's best candidate in hpart.
+// Hubs, step 2 (after the exclusive scan pcount -> poff): the same workgroups
+// reserve room for their pairs in every partition and write them, then reset
+// the staged communities to -1.
 template <class C>
-__global__ __launch_bounds__(256) void k_move_hub_part(MoveArgs<C> a)
+__global__ __launch_bounds__(256) void k_hub_fill(MoveArgs<C> a)
+{
+    typedef typename C::ST ST;
+    __shared__ int32_t hist[HUB_MAXP];
+    if (*a.done) return;
+    int h, v, beg, e0, e1, parts, gp0;
+    if (!hub_slice(a, (int)blockIdx.x, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
+    for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
+    __syncthreads();
+    int32_t *stage = a.hstage + a.hoff[h];
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+        const int c = stage[e];
+        if (c >= 0) atomicAdd(&hist[part_of(c, parts)], 1);
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < parts; p += 256)
+        if (hist[p]) hist[p] = a.poff[gp0 + p] + atomicAdd(&a.pcur[gp0 + p], hist[p]);
+    __syncthreads();
+    for (int c0 = e0; c0 < e1; c0 += 256 * 8) {
+        int c[8];
+        ST w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = c0 + (int)threadIdx.x + k * 256;
+            c[k] = e < e1 ? stage[e] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = c0 + (int)threadIdx.x + k * 256;
+            w[k] = c[k] >= 0 ? (ST)a.w[beg + e] : (ST)0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = c0 + (int)threadIdx.x + k * 256;
+            if (e >= e1) continue;
+            if (c[k] >= 0) {
+                const int pos = atomicAdd(&hist[part_of(c[k], parts)], 1);
+                a.pk[pos] = c[k];
+                a.pw[pos] = w[k];
+            }
+            stage[e] = -1;
+        }
+    }
+}
+
+// Insert (c, w) into an LDS table of 2^log2s slots holding at most cap keys
+// (counted in *cnt).  Returns false, inserting nothing, when c is absent and
+// the table already holds cap keys.
+template <typename ST>
+__device__ inline bool lds_insert_capped(int32_t *keys, ST *vals, int log2s, int32_t c, ST w,
+                                         int *cnt, int cap)
+{
+    const uint32_t mask = (1u << log2s) - 1u;
+    uint32_t h = hash32((uint32_t)c) >> (32 - log2s);
+    for (;;) {
+        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == c) {
+            atomic_add_t<ST>(&vals[h], w);
+            return true;
+        }
+        if (k < 0) {
+            if (atomicAdd(cnt, 1) >= cap) {
+                atomicSub(cnt, 1);
+                return false;
+            }
+            const int32_t old = atomicCAS(&keys[h], -1, c);
+            if (old < 0) {
+                atomic_add_t<ST>(&vals[h], w);
+                return true;
+            }
+            atomicSub(cnt, 1);
+            if (old == c) {
+                atomic_add_t<ST>(&vals[h], w);
+                return true;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Hubs, step 3: one workgroup per partition of a queued hub folds the
+// partition's pairs into an LDS table (dynamic shared memory of 2^hub_plog2
+// slots) and leaves its best candidate in hpart.  A partition with more
+// distinct communities than 3/4 of the slots (only for skewed keys) is
+// folded in several passes over sub-ranges of a third key hash, halving any
+// range that still overflows.
+template <class C>
+__global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
 {
     typedef typename C::ST ST;
     typedef typename C::SC SC;
-    constexpr int Q = HUB_SLICE / 256;
+    constexpr int LOG2S = hub_plog2<ST>();
+    constexpr int S = 1 << LOG2S;
+    constexpr int CAP = 3 * (S / 4);
+    extern __shared__ __align__(16) unsigned char smem[];
+    ST *vals = (ST *)smem;
+    int32_t *keys = (int32_t *)(smem + (size_t)S * sizeof(ST));
     __shared__ BlockRed<SC, ST, 4> r;
+    __shared__ uint64_t st_lo[40], st_hi[40];
+    __shared__ int s_sp, s_cnt, s_over;
     if (*a.done) return;
-    const int h = owner_slice(a.htslice, a.nhubs, (int)blockIdx.x);
+    const int gp = (int)blockIdx.x;
+    const int h = owner_slice(a.htslice, a.nhubs, gp);
     if (!a.hub_act[h]) return;
     const int v = a.binorder[a.list_begin + h];
-    const int d = row_len(a.off, a.deg, v);
-    const int64_t t0 = a.hoff[h];
-    const uint32_t T = (uint32_t)hub_slots(d);
-    const uint32_t s0 = (uint32_t)((int)blockIdx.x - a.htslice[h]) * HUB_SLICE;
-    int32_t *keys = a.hkeys + t0;
-    ST *vals = a.hvals + t0;
     const int dc = a.Cp[v];
     const ST kv = a.K[v];
-    int kk[Q];
-    ST xx[Q], sg[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const uint32_t s = s0 + threadIdx.x + q * 256;
-        kk[q] = s < T ? __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+    const int pb = a.poff[gp], pn = a.pcount[gp];
+    for (int s = threadIdx.x; s < S; s += 256) {
+        keys[s] = -1;
+        vals[s] = 0;
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const uint32_t s = s0 + threadIdx.x + q * 256;
-        xx[q] = kk[q] >= 0 ? __hip_atomic_load(&vals[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                           : (ST)0;
+    if (threadIdx.x == 0) {
+        st_lo[0] = 0;
+        st_hi[0] = 1ull << 32;
+        s_sp = 1;
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
     SC best = score_min<SC>();
     int bc = INT_MAX;
     ST hd = 0;
     int nk = 0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        if (kk[q] >= 0) {
-            const uint32_t s = s0 + threadIdx.x + q * 256;
-            keys[s] = -1;
-            vals[s] = 0;
-            ++nk;
+    for (;;) {
+        __syncthreads();
+        const int sp = s_sp;
+        if (sp == 0) break;
+        const uint64_t lo = st_lo[sp - 1], hi = st_hi[sp - 1];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_sp = sp - 1;
+            s_cnt = 0;
+            s_over = 0;
         }
-        consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+        __syncthreads();
+        const bool all = lo == 0 && hi == (1ull << 32);
+        for (int i = threadIdx.x; i < pn; i += 256) {
+            const int32_t c = a.pk[pb + i];
+            if (!all) {
+                const uint64_t x = hash32(mix32((uint32_t)c) ^ 0x5bd1e995u);
+                if (x < lo || x >= hi) continue;
+            }
+            if (!lds_insert_capped<ST>(keys, vals, LOG2S, c, a.pw[pb + i], &s_cnt, CAP)) s_over = 1;
+        }
+        __syncthreads();
+        if (s_over) {
+            // clear and split the range (a range of one hash value holds one key, so
+            // the splitting ends)
+            for (int s = threadIdx.x; s < S; s += 256) {
+                keys[s] = -1;
+                vals[s] = 0;
+            }
+            if (threadIdx.x == 0) {
+                const uint64_t mid = lo + (hi - lo) / 2;
+                st_lo[s_sp] = lo;
+                st_hi[s_sp] = mid;
+                st_lo[s_sp + 1] = mid;
+                st_hi[s_sp + 1] = hi;
+                s_sp += 2;
+            }
+            continue;
+        }
+        for (int s0 = threadIdx.x; s0 < S; s0 += 4 * 256) {
+            int kk[4];
+            ST xx[4], sg[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int s = s0 + q * 256;
+                kk[q] = keys[s];
+                xx[q] = kk[q] >= 0 ? vals[s] : (ST)0;
+                if (kk[q] >= 0) {
+                    keys[s] = -1;
+                    vals[s] = 0;
+                    ++nk;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+        }
     }
     block_reduce<SC, ST, 4>(r, best, bc, hd, nk);
     if (threadIdx.x == 0) {
@@ -663,12 +778,12 @@ __global__ __launch_bounds__(256) void k_move_hub_part(MoveArgs<C> a)
         p.bc = r.bc[0];
         p.hd = r.hd[0];
         p.nk = r.nonself[0];
-        ((HubPart<C> *)a.hpart)[blockIdx.x] = p;
+        ((HubPart<C> *)a.hpart)[gp] = p;
     }
 }
 
-// Hubs, step 3: one workgroup per queued hub takes the argmax over its table
-// slices and moves.
+// Hubs, step 4: one workgroup per queued hub takes the argmax over its
+// partitions and moves.
 template <class C, bool FAST>
 __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
 {
@@ -781,22 +896,34 @@ template void launch_move<CfgWideIn>(int, bool, const MoveArgs<CfgWideIn> &, int
 template void launch_move<CfgWide>(int, bool, const MoveArgs<CfgWide> &, int, int, hipStream_t);
 
 template <class C>
-void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t total_slices,
-                      int32_t table_slices, int grid, hipStream_t s)
+void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int32_t parts,
+                      int grid, int64_t *scratch, hipStream_t s)
 {
-    if (total_slices <= 0 || table_slices <= 0 || grid <= 0) return;
-    k_move_hub_scatter<C><<<total_slices, 256, 0, s>>>(a);
-    k_move_hub_part<C><<<table_slices, 256, 0, s>>>(a);
+    typedef typename C::ST ST;
+    if (sort_slices <= 0 || parts <= 0 || grid <= 0) return;
+    launch_fill_bytes_zero(a.pcount, 2 * (int64_t)parts * sizeof(int32_t), s);  // pcount, pcur
+    k_hub_count<C><<<sort_slices, 256, 0, s>>>(a);
+    launch_exclusive_scan<int32_t, int32_t>(a.pcount, a.poff, parts, scratch, nullptr, s);
+    k_hub_fill<C><<<sort_slices, 256, 0, s>>>(a);
+    const size_t bytes = ((size_t)1 << hub_plog2<ST>()) * (sizeof(ST) + 4);
+    if (bytes > 65536) {
+        // raise the dynamic-LDS limit of this kernel to what the launch asks for; a
+        // failure shows up as a launch error at the caller's check
+        if (hipFuncSetAttribute((const void *)&k_hub_part<C>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+            (void)hipGetLastError();
+    }
+    k_hub_part<C><<<parts, 256, bytes, s>>>(a);
     if (fast)
         k_move_hub<C, true><<<grid, HUB_THREADS, 0, s>>>(a);
     else
         k_move_hub<C, false><<<grid, HUB_THREADS, 0, s>>>(a);
 }
 template void launch_move_hubs<CfgNarrow>(bool, const MoveArgs<CfgNarrow> &, int32_t, int32_t,
-                                          int, hipStream_t);
+                                          int, int64_t *, hipStream_t);
 template void launch_move_hubs<CfgWideIn>(bool, const MoveArgs<CfgWideIn> &, int32_t, int32_t,
-                                          int, hipStream_t);
+                                          int, int64_t *, hipStream_t);
 template void launch_move_hubs<CfgWide>(bool, const MoveArgs<CfgWide> &, int32_t, int32_t, int,
-                                        hipStream_t);
+                                        int64_t *, hipStream_t);
 
 }  // namespace lv

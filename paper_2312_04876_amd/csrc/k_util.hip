@@ -294,6 +294,19 @@ __global__ void k_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, con
     }
 }
 
+__global__ void k_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he,
+                                 const int32_t *off, const int32_t *deg, int stbytes,
+                                 int64_t *ent, int32_t *slices, int32_t *parts)
+{
+    for (int64_t p = hb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < he;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = len_of(off, deg, binorder[p]);
+        ent[p - hb] = d;
+        slices[p - hb] = (int32_t)((d + HUB_PSLICE - 1) / HUB_PSLICE);
+        parts[p - hb] = stbytes == 4 ? hub_parts<int32_t>(d) : hub_parts<int64_t>(d);
+    }
+}
+
 // Row reductions with G lanes per row (G <= 64: groups inside a wavefront;
 // G == 256: the whole workgroup).
 template <class C, int G, int OP>
@@ -753,6 +766,15 @@ void launch_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int
     if (he > hb)
         k_hub_sizes<<<grid_for(he - hb, 256), 256, 0, s>>>(binorder, hb, he, off, deg, cap, out,
                                                            slices, tslices);
+}
+
+void launch_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
+                           const int32_t *deg, int stbytes, int64_t *ent, int32_t *slices,
+                           int32_t *parts, hipStream_t s)
+{
+    if (he > hb)
+        k_hub_move_sizes<<<grid_for(he - hb, 256), 256, 0, s>>>(binorder, hb, he, off, deg, stbytes,
+                                                                ent, slices, parts);
 }
 
 void launch_member_degrees(int32_t n, const int32_t *members, const int32_t *off,

@@ -52,6 +52,12 @@ void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, int32_t 
 // capped at cap) (aggregation caps a community's table at |Gamma|), and when
 // non-null the number of HUB_SLICE slices of the row (slices) and of the
 // table (tslices).
+// Local-moving hub bin: per hub p in [hb, he) of binorder: row length
+// (ent), sorting slices (slices) and partitions (parts, for table values of
+// stbytes bytes).
+void launch_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
+                           const int32_t *deg, int stbytes, int64_t *ent, int32_t *slices,
+                           int32_t *parts, hipStream_t s);
 void launch_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
                       const int32_t *deg, int64_t cap, int64_t *out, int32_t *slices,
                       int32_t *tslices, hipStream_t s);
@@ -96,13 +102,13 @@ struct CompactArgs {
 };
 void launch_compact(const CompactArgs &a, hipStream_t s);
 
-// Best candidate of one HUB_SLICE-slot slice of a hub's HBM table.
+// Best candidate of one partition of a hub row.
 template <class C>
 struct HubPart {
     typename C::SC best;
-    typename C::ST hd;   // weight to the own community, if its key is in the slice
+    typename C::ST hd;   // weight to the own community, if its key is in the partition
     int32_t bc;
-    int32_t nk;          // keys in the slice
+    int32_t nk;          // distinct communities in the partition
 };
 
 template <class C>
@@ -119,13 +125,16 @@ struct MoveArgs {
     uint8_t *flags_next;
     int32_t *mv_v, *mv_c, *mv_d;       // deferred moves: vertex, new and old label
     int32_t *mv_count;
-    int32_t *hkeys;                    // HBM tables of the hub bin
-    typename C::ST *hvals;
-    const int64_t *hoff;               // table offset per hub
-    const int32_t *hslice;             // first row slice per hub (exclusive scan)
-    const int32_t *htslice;            // first table slice per hub (exclusive scan)
-    const unsigned long long *htslices;  // total table slices
-    void *hpart;                       // HubPart<C> per table slice
+    // hub bin: row entries are counting-sorted into partitions by community
+    int32_t *hstage;                   // community of each hub entry (-1 between rounds)
+    const int64_t *hoff;               // first staged entry per hub (scan of row lengths)
+    const int32_t *hslice;             // first sorting slice per hub (HUB_PSLICE entries)
+    const int32_t *htslice;            // first partition per hub
+    const unsigned long long *htslices;  // total partitions
+    int32_t *pcount, *pcur, *poff;     // pairs per partition, fill cursors, offsets
+    int32_t *pk;                       // partitioned pairs (community, weight)
+    typename C::ST *pw;
+    void *hpart;                       // HubPart<C> per partition
     uint8_t *hub_act;                  // hub queued in this round
     int32_t nhubs;
     unsigned long long *spread;        // NSPREAD counter rows of SPREAD_W words
@@ -140,12 +149,13 @@ template <class C>
 void launch_move(int bin, bool fast, const MoveArgs<C> &a, int grid, int log2s_max,
                  hipStream_t s);
 int move_rows_per_block(int bin);
-// Hub bin: one workgroup per row slice (all hubs' slices, inactive ones exit),
-// one per table slice for the slice's best candidate, then one workgroup per
-// queued hub for the argmax over its slices and the move.
+// Hub bin: the queued hubs' rows are counted and sorted into partitions
+// (workgroups over all hubs' sorting slices; inactive hubs exit), one
+// workgroup per partition finds its best candidate, then one workgroup per
+// queued hub takes the argmax over its partitions and moves.
 template <class C>
-void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t total_slices,
-                      int32_t table_slices, int grid, hipStream_t s);
+void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int32_t parts,
+                      int grid, int64_t *scratch, hipStream_t s);
 
 // Deferred moves of a round (deterministic mode): each mover relabelled, and
 // the community weights and sizes updated, each workgroup combining the

@@ -32,7 +32,7 @@ struct Layout {
     size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hkeys, hvals, hsz, hoff, scratch;
-    size_t bincnt, binoff, slA, slB, mpre, hub_act, hpart;
+    size_t bincnt, binoff, slA, slB, mpre, hub_act, hpart, pcnt, poff;
 };
 
 Layout make_layout(int32_t n, int64_t nnz, int sb)
@@ -91,8 +91,11 @@ Layout make_layout(int32_t n, int64_t nnz, int sb)
     L.slB = take(4 * (n1 + 1));
     L.mpre = take(4 * (n1 + 1));
     L.hub_act = take(n1);
-    // per hub table slice (HUB_SLICE slots of a table of about 2 slots per entry)
-    L.hpart = take(32 * ((size_t)z / 512 + 64));
+    // per partition of the hub rows (at most one per 2048 entries, plus one per hub)
+    const size_t parts = (size_t)z / 512 + 64;
+    L.hpart = take(32 * parts);
+    L.pcnt = take(4 * 2 * parts);  // pcount then pcur
+    L.poff = take(4 * parts);
     L.total = cur;
     return L;
 }
@@ -160,9 +163,10 @@ struct louvain_ctx {
     int64_t *hsz, *hoff, *scratch;
     int32_t *bincnt, *binoff, *slA, *slB, *mpre;
     void *hpart;
+    int32_t *pcnt, *poff;
     uint8_t *hub_act;
     int32_t hub_slices;  // row slices of the current level's hubs
-    int32_t hub_tslices; // table slices of the current level's hubs
+    int32_t hub_tslices; // partitions of the current level's hub rows
     int64_t W;
     bool wide;
     int32_t lds_max;     // LDS row limit of the bins (LDS_MAX_NARROW or LDS_MAX_WIDE)
@@ -303,10 +307,11 @@ int setup_level(louvain_ctx *ctx)
     ctx->hub_slices = 0;
     ctx->hub_tslices = 0;
     if (hubs > 0) {
-        // HBM table offsets, row slices and table slices of the hubs (cursor and
+        // staging offsets, sorting slices and partitions of the hub rows (cursor and
         // ccount are free during moving)
-        launch_hub_sizes(ctx->binorder, ctx->bins.start[NBINS - 1], ctx->bins.start[NBINS], l.off,
-                         l.deg, INT64_MAX, ctx->hsz, ctx->cursor, ctx->ccount, s);
+        launch_hub_move_sizes(ctx->binorder, ctx->bins.start[NBINS - 1], ctx->bins.start[NBINS],
+                              l.off, l.deg, (int)sizeof(typename C::ST), ctx->hsz, ctx->cursor,
+                              ctx->ccount, s);
         launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
         launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->slA, hubs, ctx->scratch,
                                                 &ctx->sc->hub_slices, s);
@@ -367,8 +372,17 @@ int move_phase(louvain_ctx *ctx)
     a.mv_d = ctx->mv_d;
     a.spread = &ctx->sc->spread[0][0];
     a.mv_count = &ctx->sc->mv_count;
-    a.hkeys = ctx->hkeys;
-    a.hvals = (ST *)ctx->hvals;
+    a.hstage = ctx->hkeys;
+    a.pcount = ctx->pcnt;
+    a.pcur = ctx->pcnt + ctx->hub_tslices;  // zeroed together with pcount every round
+    a.poff = ctx->poff;
+    {
+        // partitioned hub pairs go to the CSR buffer the next level will be built in,
+        // which is free while this level moves
+        const int nbuf = l.buf == 0 ? 1 : 0;
+        a.pk = ctx->tgt_buf[nbuf];
+        a.pw = (ST *)ctx->w_buf[nbuf];
+    }
     a.hoff = ctx->hoff;
     a.hslice = ctx->slA;
     a.htslice = ctx->slB;
@@ -423,7 +437,8 @@ int move_phase(louvain_ctx *ctx)
                 if (b < NBINS - 1)
                     launch_move<C>(b, fast, a, grid[b], log2s[b], s);
                 else
-                    launch_move_hubs<C>(fast, a, ctx->hub_slices, ctx->hub_tslices, grid[b], s);
+                    launch_move_hubs<C>(fast, a, ctx->hub_slices, ctx->hub_tslices, grid[b], ctx->scratch,
+                                        s);
                 CKL();
                 TRY(prof_end(ctx, F_MOVE0 + b, ev));
             }
@@ -875,6 +890,8 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     ctx->slA = (int32_t *)(b + L.slA);
     ctx->slB = (int32_t *)(b + L.slB);
     ctx->hpart = (void *)(b + L.hpart);
+    ctx->pcnt = (int32_t *)(b + L.pcnt);
+    ctx->poff = (int32_t *)(b + L.poff);
     ctx->mpre = (int32_t *)(b + L.mpre);
     ctx->hub_act = b + L.hub_act;
     // the scalar block keeps W; the hash slab starts empty and every user clears what it used
