@@ -48,12 +48,6 @@ constexpr int LDS_MAX_NARROW = 8192;
 constexpr int LDS_MAX_WIDE = 4096;
 constexpr int HUB_THREADS = 256;
 constexpr int BLOCK_THREADS = 512;
-// Hub rows (and hub communities in aggregation) are cut into slices of
-// HUB_SLICE entries; one workgroup folds a slice into an LDS table of
-// 2^HUB_LOG2S slots and then merges it into the row's HBM table, so repeated
-// communities are combined in LDS before they reach HBM atomics.
-constexpr int HUB_SLICE = 2048;
-constexpr int HUB_LOG2S = 12;
 // Hub rows in local moving are not put in HBM hashtables: each round, the
 // (community, weight) pairs of a queued hub's row are counting-sorted into
 // partitions by a hash of the community, and one workgroup per partition
@@ -74,6 +68,10 @@ __host__ __device__ inline int hub_parts(int64_t d)
     const int64_t p = (d + hub_part_pairs<ST>() - 1) / hub_part_pairs<ST>();
     return (int)(p < 1 ? 1 : (p > HUB_MAXP ? HUB_MAXP : p));
 }
+// Aggregation windows of hub communities: AGG_PSLICE = 2^AGG_PLOG2 flattened
+// member entries, folded in a table of twice as many slots.
+constexpr int AGG_PLOG2 = 12;
+constexpr int AGG_PSLICE = 1 << AGG_PLOG2;
 // Rows per workgroup of the binning and compaction kernels.
 constexpr int BIN_CHUNK = 4096;
 // Vertices per workgroup (and LDS table slots / 2) of the community counting kernels.
@@ -112,8 +110,6 @@ __host__ __device__ inline int block_log2s(int d)
     return l;
 }
 
-// HBM table size for a hub row of length d (a multiple of 64, >= 2d).
-__host__ __device__ inline int64_t hub_slots(int64_t d) { return ((2 * d + 63) / 64) * 64; }
 
 // ---------------------------------------------------------------------------
 // Scalars shared between kernels and the host (one copy in the workspace).
@@ -337,6 +333,41 @@ __device__ inline i128 wave_sum_i128(i128 x)
 {
     for (int o = 32; o > 0; o >>= 1) x += shfl_xor_t<i128>(x, o);
     return x;
+}
+
+// Insert (c, w) into an LDS table of 2^log2s slots holding at most cap keys
+// (counted in *cnt).  Returns false, inserting nothing, when c is absent and
+// the table already holds cap keys.
+template <typename ST>
+__device__ inline bool lds_insert_capped(int32_t *keys, ST *vals, int log2s, int32_t c, ST w,
+                                         int *cnt, int cap)
+{
+    const uint32_t mask = (1u << log2s) - 1u;
+    uint32_t h = hash32((uint32_t)c) >> (32 - log2s);
+    for (;;) {
+        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == c) {
+            atomic_add_t<ST>(&vals[h], w);
+            return true;
+        }
+        if (k < 0) {
+            if (atomicAdd(cnt, 1) >= cap) {
+                atomicSub(cnt, 1);
+                return false;
+            }
+            const int32_t old = atomicCAS(&keys[h], -1, c);
+            if (old < 0) {
+                atomic_add_t<ST>(&vals[h], w);
+                return true;
+            }
+            atomicSub(cnt, 1);
+            if (old == c) {
+                atomic_add_t<ST>(&vals[h], w);
+                return true;
+            }
+        }
+        h = (h + 1) & mask;
+    }
 }
 
 }  // namespace lv

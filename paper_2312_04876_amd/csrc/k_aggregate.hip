@@ -36,27 +36,6 @@ __device__ inline void lds_add(int32_t *keys, ST *vals, int log2s, int32_t c, ST
     }
 }
 
-template <typename ST>
-__device__ inline void hbm_add(int32_t *keys, ST *vals, uint32_t T, int32_t c, ST w)
-{
-    uint32_t h = (uint32_t)(((uint64_t)hash32((uint32_t)c) * (uint64_t)T) >> 32);
-    for (;;) {
-        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (k == c) {
-            atomic_add_t<ST>(&vals[h], w);
-            return;
-        }
-        if (k < 0) {
-            const int32_t old = atomicCAS(&keys[h], -1, c);
-            if (old < 0 || old == c) {
-                atomic_add_t<ST>(&vals[h], w);
-                return;
-            }
-        }
-        h = (h + 1 == T) ? 0u : h + 1;
-    }
-}
-
 // Position of the member owning flattened entry t: the first lane whose
 // inclusive prefix exceeds t.
 __device__ inline int owner_of(const int32_t *incl, int n, int t)
@@ -271,33 +250,24 @@ __global__ __launch_bounds__(256) void k_agg_block(AggArgs<C> a, int log2s_max)
     }
 }
 
-// Bin 5 (hub communities), step 1: one workgroup per HUB_SLICE-entry window of
-// the concatenated member rows of a community (window w of community idx is
-// slice cslice[idx] + w); the window is folded into an LDS table and the table
-// is added into the community's HBM table of hub_slots(min(total, |Gamma|))
-// slots at hoff[idx].
-template <class C>
-__global__ __launch_bounds__(256) void k_agg_hub_scatter(AggArgs<C> a, int32_t nh)
+// Hub communities (bin 6) are folded like hub rows in local moving: the
+// flattened member rows of each community, folded per window, are
+// counting-sorted into hash partitions, and one workgroup per partition folds
+// it in LDS and appends its keys to the community's row.
+
+// Walks the flattened entries t in [w0, w1) of community c's member rows
+// (members mb..me, flattened offsets mpre - base): f(t, e) for CSR entry e.
+// All threads of the workgroup call this.
+struct Window {
+    int32_t start[257];
+    int32_t rb[256];
+    int32_t m0;
+};
+
+template <class C, class F>
+__device__ inline void walk_window(const AggArgs<C> &a, Window &W, int mb, int me, int base, int w0,
+                                   int w1, unsigned long long *nm_, F f)
 {
-    typedef typename C::ST ST;
-    constexpr int S = 1 << HUB_LOG2S;
-    __shared__ ST s_vals[S];
-    __shared__ int32_t s_keys[S];
-    __shared__ int32_t s_start[257];
-    __shared__ int32_t s_rb[256];
-    __shared__ int32_t s_m0;
-    const int k = (int)blockIdx.x;
-    const int idx = owner_slice(a.cslice, nh, k);
-    const int c = a.cbinorder[a.begin + idx];
-    const int mb = a.coff[c], me = a.coff[c + 1];
-    const int base = a.mpre[mb];
-    const int tot = a.mpre[me] - base;
-    const int w0 = (k - a.cslice[idx]) * HUB_SLICE;
-    const int w1 = min(w0 + HUB_SLICE, tot);
-    for (int s = threadIdx.x; s < S; s += 256) {
-        s_keys[s] = -1;
-        s_vals[s] = 0;
-    }
     if (threadIdx.x == 0) {
         // first member whose row ends after w0
         int lo = mb, hi = me - 1;
@@ -308,43 +278,98 @@ __global__ __launch_bounds__(256) void k_agg_hub_scatter(AggArgs<C> a, int32_t n
             else
                 lo = mid + 1;
         }
-        s_m0 = lo;
+        W.m0 = lo;
     }
     __syncthreads();
-    unsigned long long ne_ = 0, nm_ = 0;
-    int m = s_m0;
+    int m = W.m0;
     for (;;) {
         const int cnt = min(256, me - m);
         if ((int)threadIdx.x < cnt) {
             const int u = a.members[m + threadIdx.x];
-            s_rb[threadIdx.x] = a.off[u];
+            W.rb[threadIdx.x] = a.off[u];
             const int st = a.mpre[m + threadIdx.x] - base;
-            s_start[threadIdx.x] = st;
-            if (st >= w0 && st < w1 && a.mpre[m + threadIdx.x + 1] - base > st) ++nm_;
+            W.start[threadIdx.x] = st;
+            if (nm_ && st >= w0 && st < w1 && a.mpre[m + threadIdx.x + 1] - base > st) ++*nm_;
         }
-        if (threadIdx.x == 0) s_start[cnt] = a.mpre[m + cnt] - base;
+        if (threadIdx.x == 0) W.start[cnt] = a.mpre[m + cnt] - base;
         __syncthreads();
-        const int t_lo = max(w0, s_start[0]);
-        const int t_hi = min(w1, s_start[cnt]);
+        const int t_lo = max(w0, W.start[0]);
+        const int t_hi = min(w1, W.start[cnt]);
         for (int t = t_lo + (int)threadIdx.x; t < t_hi; t += 256) {
-            const int L = owner_slice(s_start, cnt, t);
-            const int e = s_rb[L] + (t - s_start[L]);
-            lds_add<ST>(s_keys, s_vals, HUB_LOG2S, a.Cp[a.tgt[e]], (ST)a.w[e]);
-            ++ne_;
+            const int L = owner_slice(W.start, cnt, t);
+            f(t, W.rb[L] + (t - W.start[L]));
         }
-        const bool more = s_start[cnt] < w1 && m + cnt < me;
+        const bool more = W.start[cnt] < w1 && m + cnt < me;
         __syncthreads();
         if (!more) break;
         m += cnt;
     }
-    int64_t cap = tot;
-    if (cap > a.ncomm) cap = a.ncomm;
-    const uint32_t T = (uint32_t)hub_slots(cap);
-    const int64_t t0 = a.hoff[idx];
-    for (int s = threadIdx.x; s < S; s += 256) {
-        const int key = s_keys[s];
-        if (key >= 0) hbm_add<ST>(a.hkeys + t0, a.hvals + t0, T, key, s_vals[s]);
+}
+
+// Sorting window k of the hub bin: community idx (in the bin), c, members,
+// flattened range [w0, w1), partitions.
+template <class C>
+__device__ inline void agg_window(const AggArgs<C> &a, int nh, int k, int *idx, int *c, int *mb,
+                                  int *me, int *base, int *w0, int *w1, int *parts, int *gp0)
+{
+    *idx = owner_slice(a.cslice, nh, k);
+    *c = a.cbinorder[a.begin + *idx];
+    *mb = a.coff[*c];
+    *me = a.coff[*c + 1];
+    *base = a.mpre[*mb];
+    const int tot = a.mpre[*me] - *base;
+    *w0 = (k - a.cslice[*idx]) * AGG_PSLICE;
+    *w1 = min(*w0 + AGG_PSLICE, tot);
+    *gp0 = a.tslice[*idx];
+    *parts = (*idx + 1 < nh ? a.tslice[*idx + 1] : (int)*a.tslices) - *gp0;
+}
+
+// Step 1: one workgroup per AGG_PSLICE flattened entries of a hub community
+// folds its window in an LDS table (dynamic shared memory of 2 * AGG_PSLICE
+// slots), stages the window's distinct (community, weight) pairs at the
+// window's flattened offset (count in wcnt), and adds their count per
+// partition into pcount.  Folding first keeps a community's many entries
+// into the same neighbour (its internal edges above all) to one pair per
+// window.
+template <class C>
+__global__ __launch_bounds__(256) void k_agg_hub_count(AggArgs<C> a, int32_t nh)
+{
+    typedef typename C::ST ST;
+    constexpr int LOG2S = AGG_PLOG2 + 1;
+    constexpr int S = 1 << LOG2S;
+    extern __shared__ __align__(16) unsigned char smem[];
+    ST *vals = (ST *)smem;
+    int32_t *keys = (int32_t *)(smem + (size_t)S * sizeof(ST));
+    __shared__ Window W;
+    __shared__ int32_t hist[HUB_MAXP];
+    __shared__ int s_n;
+    int idx, c, mb, me, base, w0, w1, parts, gp0;
+    agg_window(a, nh, (int)blockIdx.x, &idx, &c, &mb, &me, &base, &w0, &w1, &parts, &gp0);
+    for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
+    for (int q = threadIdx.x; q < S; q += 256) {
+        keys[q] = -1;
+        vals[q] = 0;
     }
+    if (threadIdx.x == 0) s_n = 0;
+    unsigned long long ne_ = 0, nm_ = 0;
+    walk_window(a, W, mb, me, base, w0, w1, &nm_, [&](int t, int e) {
+        lds_add<ST>(keys, vals, LOG2S, a.Cp[a.tgt[e]], (ST)a.w[e]);
+        ++ne_;
+    });
+    int32_t *sk = a.hstage + base + w0;
+    ST *sw = a.hstage_w + base + w0;
+    for (int q = threadIdx.x; q < S; q += 256) {
+        const int32_t key = keys[q];
+        if (key < 0) continue;
+        const int i = atomicAdd(&s_n, 1);
+        sk[i] = key;
+        sw[i] = vals[q];
+        atomicAdd(&hist[part_of(key, parts)], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.wcnt[blockIdx.x] = s_n;
+    for (int p = threadIdx.x; p < parts; p += 256)
+        if (hist[p]) atomicAdd(&a.pcount[gp0 + p], hist[p]);
     nm_ = wave_sum_u64(nm_);
     ne_ = wave_sum_u64(ne_);
     if ((threadIdx.x & 63) == 0) {
@@ -353,53 +378,120 @@ __global__ __launch_bounds__(256) void k_agg_hub_scatter(AggArgs<C> a, int32_t n
     }
 }
 
-// Bin 5, step 2: one workgroup per HUB_SLICE slots of a community's HBM table
-// (slice tslice[idx] + j) appends the occupied slots to row c of the
-// super-vertex graph (position from an atomic on ydeg[c], zero on entry) and
-// clears them.
+// Step 2 (after the exclusive scan pcount -> poff): the same workgroups
+// reserve room in every partition and move their staged pairs there.
 template <class C>
-__global__ __launch_bounds__(256) void k_agg_hub_emit(AggArgs<C> a, int32_t nh)
+__global__ __launch_bounds__(256) void k_agg_hub_fill(AggArgs<C> a, int32_t nh)
 {
     typedef typename C::ST ST;
-    __shared__ ST s_v[HUB_SLICE];
-    __shared__ int32_t s_k[HUB_SLICE];
-    __shared__ int32_t s_cnt, s_base;
-    const int k = (int)blockIdx.x;
-    const int idx = owner_slice(a.tslice, nh, k);
-    const int c = a.cbinorder[a.begin + idx];
-    int64_t cap = a.yoff[c + 1] - a.yoff[c];
-    if (cap > a.ncomm) cap = a.ncomm;
-    const uint32_t T = (uint32_t)hub_slots(cap);
-    const int64_t t0 = a.hoff[idx];
-    int32_t *keys = a.hkeys + t0;
-    ST *vals = a.hvals + t0;
-    const uint32_t s0 = (uint32_t)(k - a.tslice[idx]) * HUB_SLICE;
-    const uint32_t s1 = min(s0 + (uint32_t)HUB_SLICE, T);
-    if (threadIdx.x == 0) s_cnt = 0;
+    __shared__ int32_t hist[HUB_MAXP];
+    int idx, c, mb, me, base, w0, w1, parts, gp0;
+    agg_window(a, nh, (int)blockIdx.x, &idx, &c, &mb, &me, &base, &w0, &w1, &parts, &gp0);
+    for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
     __syncthreads();
-    for (uint32_t s = s0 + threadIdx.x; s < s1; s += 256) {
-        const int key = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (key >= 0) {
-            const ST x = __hip_atomic_load(&vals[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int pos = atomicAdd(&s_cnt, 1);
-            s_k[pos] = key;
-            s_v[pos] = x;
+    const int n = a.wcnt[blockIdx.x];
+    const int32_t *sk = a.hstage + base + w0;
+    const ST *sw = a.hstage_w + base + w0;
+    for (int i = threadIdx.x; i < n; i += 256) atomicAdd(&hist[part_of(sk[i], parts)], 1);
+    __syncthreads();
+    for (int p = threadIdx.x; p < parts; p += 256)
+        if (hist[p]) hist[p] = a.poff[gp0 + p] + atomicAdd(&a.pcur[gp0 + p], hist[p]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int32_t key = sk[i];
+        const int pos = atomicAdd(&hist[part_of(key, parts)], 1);
+        a.pk[pos] = key;
+        a.pw[pos] = sw[i];
+    }
+}
+
+// Step 3: one workgroup per partition folds its pairs into an LDS table of
+// 2^hub_plog2 slots and appends the keys to row c (position from an atomic on
+// ydeg[c], zero on entry).  A partition with more distinct keys than 3/4 of
+// the slots is folded in passes over halved ranges of a third key hash.
+template <class C>
+__global__ __launch_bounds__(256) void k_agg_hub_part(AggArgs<C> a, int32_t nh)
+{
+    typedef typename C::ST ST;
+    constexpr int LOG2S = hub_plog2<ST>();
+    constexpr int S = 1 << LOG2S;
+    __shared__ ST vals[S];
+    __shared__ int32_t keys[S];
+    __shared__ uint64_t st_lo[40], st_hi[40];
+    __shared__ int s_sp, s_cnt, s_over, s_pos, s_base;
+    const int gp = (int)blockIdx.x;
+    const int idx = owner_slice(a.tslice, nh, gp);
+    const int c = a.cbinorder[a.begin + idx];
+    const int pb = a.poff[gp], pn = a.pcount[gp];
+    // table of 2^lg slots: twice the pairs (so no overflow) when that fits
+    int lg = 8;
+    while (lg < LOG2S && (1 << lg) < 2 * pn) ++lg;
+    const int Su = 1 << lg, capu = 3 * (Su / 4);
+    for (int s = threadIdx.x; s < Su; s += 256) {
+        keys[s] = -1;
+        vals[s] = 0;
+    }
+    if (threadIdx.x == 0) {
+        st_lo[0] = 0;
+        st_hi[0] = 1ull << 32;
+        s_sp = 1;
+    }
+    unsigned long long emitted = 0;
+    for (;;) {
+        __syncthreads();
+        const int sp = s_sp;
+        if (sp == 0) break;
+        const uint64_t lo = st_lo[sp - 1], hi = st_hi[sp - 1];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_sp = sp - 1;
+            s_cnt = 0;
+            s_over = 0;
+            s_pos = 0;
+        }
+        __syncthreads();
+        const bool all = lo == 0 && hi == (1ull << 32);
+        for (int i = threadIdx.x; i < pn; i += 256) {
+            const int32_t key = a.pk[pb + i];
+            if (!all) {
+                const uint64_t x = hash32(mix32((uint32_t)key) ^ 0x5bd1e995u);
+                if (x < lo || x >= hi) continue;
+            }
+            if (!lds_insert_capped<ST>(keys, vals, lg, key, a.pw[pb + i], &s_cnt, capu)) s_over = 1;
+        }
+        __syncthreads();
+        if (s_over) {
+            for (int s = threadIdx.x; s < Su; s += 256) {
+                keys[s] = -1;
+                vals[s] = 0;
+            }
+            if (threadIdx.x == 0) {
+                const uint64_t mid = lo + (hi - lo) / 2;
+                st_lo[s_sp] = lo;
+                st_hi[s_sp] = mid;
+                st_lo[s_sp + 1] = mid;
+                st_hi[s_sp + 1] = hi;
+                s_sp += 2;
+            }
+            continue;
+        }
+        if (threadIdx.x == 0) s_base = s_cnt ? atomicAdd(&a.ydeg[c], s_cnt) : 0;
+        __syncthreads();
+        const int64_t ybeg = (int64_t)a.yoff[c] + s_base;
+        for (int s = threadIdx.x; s < Su; s += 256) {
+            const int32_t key = keys[s];
+            if (key < 0) continue;
+            const int q = atomicAdd(&s_pos, 1);
+            a.ytgt[ybeg + q] = key;
+            a.yw[ybeg + q] = vals[s];
             keys[s] = -1;
             vals[s] = 0;
+            ++emitted;
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        s_base = s_cnt ? atomicAdd(&a.ydeg[c], s_cnt) : 0;
-        if (s_cnt) atomicAdd(&a.work[3], (unsigned long long)s_cnt);
-        if (s0 == 0) atomicAdd(&a.work[0], 1ull);
-    }
-    __syncthreads();
-    const int ybeg = a.yoff[c] + s_base;
-    for (int i = threadIdx.x; i < s_cnt; i += 256) {
-        a.ytgt[ybeg + i] = s_k[i];
-        a.yw[ybeg + i] = s_v[i];
-    }
+    emitted = wave_sum_u64(emitted);
+    if ((threadIdx.x & 63) == 0 && emitted) atomicAdd(&a.work[3], emitted);
+    if (threadIdx.x == 0 && gp == a.tslice[idx]) atomicAdd(&a.work[0], 1ull);
 }
 
 inline int agg_grid(int count, int per_block)
@@ -440,22 +532,34 @@ void launch_aggregate(int bin, const AggArgs<C> &a, int log2s_max, hipStream_t s
 }
 
 template <class C>
-void launch_aggregate_hub(const AggArgs<C> &a, int32_t row_slices, int32_t table_slices,
-                          hipStream_t s)
+void launch_aggregate_hub(const AggArgs<C> &a, int32_t sort_slices, int32_t parts,
+                          int64_t *scratch, hipStream_t s)
 {
-    if (a.count <= 0 || row_slices <= 0) return;
-    k_agg_hub_scatter<C><<<row_slices, 256, 0, s>>>(a, a.count);
-    k_agg_hub_emit<C><<<table_slices, 256, 0, s>>>(a, a.count);
+    if (a.count <= 0 || sort_slices <= 0 || parts <= 0) return;
+    typedef typename C::ST ST;
+    launch_fill_bytes_zero(a.pcount, 2 * (int64_t)parts * sizeof(int32_t), s);  // pcount, pcur
+    const size_t bytes = ((size_t)2 << AGG_PLOG2) * (sizeof(ST) + 4);
+    if (bytes > 32768) {
+        // raise the dynamic-LDS limit of this kernel to what the launch asks for; a
+        // failure shows up as a launch error at the caller's check
+        if (hipFuncSetAttribute((const void *)&k_agg_hub_count<C>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+            (void)hipGetLastError();
+    }
+    k_agg_hub_count<C><<<sort_slices, 256, bytes, s>>>(a, a.count);
+    launch_exclusive_scan<int32_t, int32_t>(a.pcount, a.poff, parts, scratch, nullptr, s);
+    k_agg_hub_fill<C><<<sort_slices, 256, 0, s>>>(a, a.count);
+    k_agg_hub_part<C><<<parts, 256, 0, s>>>(a, a.count);
 }
 
 template void launch_aggregate<CfgNarrow>(int, const AggArgs<CfgNarrow> &, int, hipStream_t);
 template void launch_aggregate<CfgWideIn>(int, const AggArgs<CfgWideIn> &, int, hipStream_t);
 template void launch_aggregate<CfgWide>(int, const AggArgs<CfgWide> &, int, hipStream_t);
 template void launch_aggregate_hub<CfgNarrow>(const AggArgs<CfgNarrow> &, int32_t, int32_t,
-                                              hipStream_t);
+                                              int64_t *, hipStream_t);
 template void launch_aggregate_hub<CfgWideIn>(const AggArgs<CfgWideIn> &, int32_t, int32_t,
-                                              hipStream_t);
+                                              int64_t *, hipStream_t);
 template void launch_aggregate_hub<CfgWide>(const AggArgs<CfgWide> &, int32_t, int32_t,
-                                            hipStream_t);
+                                            int64_t *, hipStream_t);
 
 }  // namespace lv

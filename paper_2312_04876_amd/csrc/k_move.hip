@@ -588,8 +588,7 @@ __global__ __launch_bounds__(256) void k_hub_count(MoveArgs<C> a)
 }
 
 // Hubs, step 2 (after the exclusive scan pcount -> poff): the same workgroups
-// reserve room for their pairs in every partition and write them, then reset
-// the staged communities to -1.
+// reserve room for their pairs in every partition and write them.
 template <class C>
 __global__ __launch_bounds__(256) void k_hub_fill(MoveArgs<C> a)
 {
@@ -631,43 +630,7 @@ __global__ __launch_bounds__(256) void k_hub_fill(MoveArgs<C> a)
                 a.pk[pos] = c[k];
                 a.pw[pos] = w[k];
             }
-            stage[e] = -1;
         }
-    }
-}
-
-// Insert (c, w) into an LDS table of 2^log2s slots holding at most cap keys
-// (counted in *cnt).  Returns false, inserting nothing, when c is absent and
-// the table already holds cap keys.
-template <typename ST>
-__device__ inline bool lds_insert_capped(int32_t *keys, ST *vals, int log2s, int32_t c, ST w,
-                                         int *cnt, int cap)
-{
-    const uint32_t mask = (1u << log2s) - 1u;
-    uint32_t h = hash32((uint32_t)c) >> (32 - log2s);
-    for (;;) {
-        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k == c) {
-            atomic_add_t<ST>(&vals[h], w);
-            return true;
-        }
-        if (k < 0) {
-            if (atomicAdd(cnt, 1) >= cap) {
-                atomicSub(cnt, 1);
-                return false;
-            }
-            const int32_t old = atomicCAS(&keys[h], -1, c);
-            if (old < 0) {
-                atomic_add_t<ST>(&vals[h], w);
-                return true;
-            }
-            atomicSub(cnt, 1);
-            if (old == c) {
-                atomic_add_t<ST>(&vals[h], w);
-                return true;
-            }
-        }
-        h = (h + 1) & mask;
     }
 }
 
@@ -684,7 +647,6 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
     typedef typename C::SC SC;
     constexpr int LOG2S = hub_plog2<ST>();
     constexpr int S = 1 << LOG2S;
-    constexpr int CAP = 3 * (S / 4);
     extern __shared__ __align__(16) unsigned char smem[];
     ST *vals = (ST *)smem;
     int32_t *keys = (int32_t *)(smem + (size_t)S * sizeof(ST));
@@ -699,7 +661,11 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
     const int dc = a.Cp[v];
     const ST kv = a.K[v];
     const int pb = a.poff[gp], pn = a.pcount[gp];
-    for (int s = threadIdx.x; s < S; s += 256) {
+    // table of 2^lg slots: twice the pairs (so no overflow) when that fits
+    int lg = 8;
+    while (lg < LOG2S && (1 << lg) < 2 * pn) ++lg;
+    const int Su = 1 << lg, capu = 3 * (Su / 4);
+    for (int s = threadIdx.x; s < Su; s += 256) {
         keys[s] = -1;
         vals[s] = 0;
     }
@@ -731,13 +697,13 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
                 const uint64_t x = hash32(mix32((uint32_t)c) ^ 0x5bd1e995u);
                 if (x < lo || x >= hi) continue;
             }
-            if (!lds_insert_capped<ST>(keys, vals, LOG2S, c, a.pw[pb + i], &s_cnt, CAP)) s_over = 1;
+            if (!lds_insert_capped<ST>(keys, vals, lg, c, a.pw[pb + i], &s_cnt, capu)) s_over = 1;
         }
         __syncthreads();
         if (s_over) {
             // clear and split the range (a range of one hash value holds one key, so
             // the splitting ends)
-            for (int s = threadIdx.x; s < S; s += 256) {
+            for (int s = threadIdx.x; s < Su; s += 256) {
                 keys[s] = -1;
                 vals[s] = 0;
             }
@@ -751,13 +717,13 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
             }
             continue;
         }
-        for (int s0 = threadIdx.x; s0 < S; s0 += 4 * 256) {
+        for (int s0 = threadIdx.x; s0 < Su; s0 += 4 * 256) {
             int kk[4];
             ST xx[4], sg[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int s = s0 + q * 256;
-                kk[q] = keys[s];
+                kk[q] = s < Su ? keys[s] : -1;
                 xx[q] = kk[q] >= 0 ? vals[s] : (ST)0;
                 if (kk[q] >= 0) {
                     keys[s] = -1;

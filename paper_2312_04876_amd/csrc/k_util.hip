@@ -129,18 +129,6 @@ __global__ void k_iota(int32_t *p, int64_t n)
         p[i] = (int32_t)i;
 }
 
-__global__ void k_init_slab(int32_t *keys, unsigned char *vals, int64_t slots, int vbytes)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < slots;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        keys[i] = -1;
-        if (vbytes == 8)
-            ((int64_t *)vals)[i] = 0;
-        else
-            ((int32_t *)vals)[i] = 0;
-    }
-}
-
 __global__ __launch_bounds__(256) void k_validate(int32_t n, int64_t nnz, const int32_t *off,
                                                   const int32_t *tgt, const int32_t *w,
                                                   int32_t *err, unsigned long long *W)
@@ -279,30 +267,16 @@ __global__ __launch_bounds__(256) void k_bin_fill(int32_t n, const int32_t *off,
     }
 }
 
-__global__ void k_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
-                            const int32_t *deg, int64_t cap, int64_t *out, int32_t *slices,
-                            int32_t *tslices)
-{
-    for (int64_t p = hb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < he;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t len = len_of(off, deg, binorder[p]);
-        const int64_t d = len > cap ? cap : len;
-        const int64_t T = hub_slots(d);
-        out[p - hb] = T;
-        if (slices) slices[p - hb] = (int32_t)((len + HUB_SLICE - 1) / HUB_SLICE);
-        if (tslices) tslices[p - hb] = (int32_t)((T + HUB_SLICE - 1) / HUB_SLICE);
-    }
-}
 
 __global__ void k_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he,
                                  const int32_t *off, const int32_t *deg, int stbytes,
-                                 int64_t *ent, int32_t *slices, int32_t *parts)
+                                 int64_t *ent, int32_t *slices, int32_t *parts, int slice)
 {
     for (int64_t p = hb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < he;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = len_of(off, deg, binorder[p]);
         ent[p - hb] = d;
-        slices[p - hb] = (int32_t)((d + HUB_PSLICE - 1) / HUB_PSLICE);
+        slices[p - hb] = (int32_t)((d + slice - 1) / slice);
         parts[p - hb] = stbytes == 4 ? hub_parts<int32_t>(d) : hub_parts<int64_t>(d);
     }
 }
@@ -718,11 +692,6 @@ void launch_iota(int32_t *p, int64_t n, hipStream_t s)
     if (n > 0) k_iota<<<grid_for(n, 256), 256, 0, s>>>(p, n);
 }
 
-void launch_init_hash_slab(int32_t *keys, void *vals, int64_t slots, int vbytes, hipStream_t s)
-{
-    if (slots > 0)
-        k_init_slab<<<grid_for(slots, 256), 256, 0, s>>>(keys, (unsigned char *)vals, slots, vbytes);
-}
 
 void launch_validate(int32_t n, int64_t nnz, const int32_t *off, const int32_t *tgt,
                      const int32_t *w, int32_t *err, unsigned long long *W, hipStream_t s)
@@ -759,22 +728,14 @@ void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, int32_t 
     if (G > 0) k_bin_fill<<<G, 256, 0, s>>>(n, off, deg, boff, G, lds_max, binorder);
 }
 
-void launch_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
-                      const int32_t *deg, int64_t cap, int64_t *out, int32_t *slices,
-                      int32_t *tslices, hipStream_t s)
-{
-    if (he > hb)
-        k_hub_sizes<<<grid_for(he - hb, 256), 256, 0, s>>>(binorder, hb, he, off, deg, cap, out,
-                                                           slices, tslices);
-}
 
 void launch_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
                            const int32_t *deg, int stbytes, int64_t *ent, int32_t *slices,
-                           int32_t *parts, hipStream_t s)
+                           int32_t *parts, hipStream_t s, int slice)
 {
     if (he > hb)
         k_hub_move_sizes<<<grid_for(he - hb, 256), 256, 0, s>>>(binorder, hb, he, off, deg, stbytes,
-                                                                ent, slices, parts);
+                                                                ent, slices, parts, slice);
 }
 
 void launch_member_degrees(int32_t n, const int32_t *members, const int32_t *off,

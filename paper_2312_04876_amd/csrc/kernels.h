@@ -24,7 +24,6 @@ void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_iota(int32_t *p, int64_t n, hipStream_t s);
-void launch_init_hash_slab(int32_t *keys, void *vals, int64_t slots, int vbytes, hipStream_t s);
 
 // Validation of the input CSR; sets bits of *err and adds weights into *W.
 void launch_validate(int32_t n, int64_t nnz, const int32_t *off, const int32_t *tgt,
@@ -47,20 +46,12 @@ void launch_bin_count(int32_t n, const int32_t *off, const int32_t *deg, int32_t
                       int32_t *maxlen, hipStream_t s);
 void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, int32_t lds_max,
                      const int32_t *boff, int32_t *binorder, hipStream_t s);
-
-// For the rows binorder[hb .. he): HBM table sizes out[p-hb] = hub_slots(len
-// capped at cap) (aggregation caps a community's table at |Gamma|), and when
-// non-null the number of HUB_SLICE slices of the row (slices) and of the
-// table (tslices).
-// Local-moving hub bin: per hub p in [hb, he) of binorder: row length
-// (ent), sorting slices (slices) and partitions (parts, for table values of
-// stbytes bytes).
+// Hub bin rows binorder[hb .. he) (row lengths from off/deg, or from deg alone
+// when off is null): length (ent), sorting slices of `slice` entries (slices)
+// and hash partitions (parts, for table values of stbytes bytes).
 void launch_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
                            const int32_t *deg, int stbytes, int64_t *ent, int32_t *slices,
-                           int32_t *parts, hipStream_t s);
-void launch_hub_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
-                      const int32_t *deg, int64_t cap, int64_t *out, int32_t *slices,
-                      int32_t *tslices, hipStream_t s);
+                           int32_t *parts, hipStream_t s, int slice = HUB_PSLICE);
 
 // mdeg[m] = row length of members[m].
 void launch_member_degrees(int32_t n, const int32_t *members, const int32_t *off,
@@ -193,23 +184,28 @@ struct AggArgs {
     int32_t *ydeg;                    // used length of each row of G''
     int32_t *ytgt;
     typename C::ST *yw;
-    int32_t *hkeys;
-    typename C::ST *hvals;
-    const int64_t *hoff;
-    const int32_t *mpre;              // hub bin: exclusive scan of member row lengths
-    const int32_t *cslice, *tslice;   // hub bin: first row slice / table slice per community
-    int32_t ncomm;                    // |Gamma| (caps hub table sizes)
+    // hub bin: flattened member rows counting-sorted into partitions by community
+    const int32_t *mpre;              // exclusive scan of member row lengths
+    const int32_t *cslice, *tslice;   // first sorting slice / partition per community
+    const unsigned long long *tslices;  // total partitions
+    int32_t *hstage;                  // distinct pairs of each window (at its flattened offset)
+    typename C::ST *hstage_w;
+    int32_t *wcnt;                    // pairs staged per window
+    int32_t *pcount, *pcur, *poff;    // pairs per partition, fill cursors, offsets
+    int32_t *pk;                      // partitioned pairs (community, weight)
+    typename C::ST *pw;
+    int32_t ncomm;                    // |Gamma|
     unsigned long long *work;         // [communities, members, entries, emitted]
 };
 // Bins 0-4 (LDS tables); the hub bin goes through launch_aggregate_hub.
 // log2s_max: LDS table size of bin 4.
 template <class C>
 void launch_aggregate(int bin, const AggArgs<C> &a, int log2s_max, hipStream_t s);
-// Bin 5: HBM tables of hub_slots(min(total degree, ncomm)) slots at hoff[index in bin];
-// one workgroup per HUB_SLICE entries of a community's member rows, then one per
-// HUB_SLICE table slots to write the row.
+// Hub bin: one workgroup per AGG_PSLICE flattened entries of a community's
+// member rows folds and stages them and then sorts them into partitions; one
+// workgroup per partition folds it and appends its keys to the community's row.
 template <class C>
-void launch_aggregate_hub(const AggArgs<C> &a, int32_t row_slices, int32_t table_slices,
-                          hipStream_t s);
+void launch_aggregate_hub(const AggArgs<C> &a, int32_t sort_slices, int32_t parts,
+                          int64_t *scratch, hipStream_t s);
 
 }  // namespace lv

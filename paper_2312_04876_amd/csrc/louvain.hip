@@ -27,11 +27,11 @@ constexpr size_t ALIGN = 256;
 struct Layout {
     size_t total;
     int sb;  // bytes of K', Sigma', table values and aggregated weights (4 or 8)
-    int64_t slots, scratch_elems;
+    int64_t scratch_elems;
     size_t scalars, Cp, top, K, Sig, size, fa, fb, binorder, worklist, mv_v, mv_c, mv_d;
     size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
-    size_t hkeys, hvals, hsz, hoff, scratch;
+    size_t hstage, hstage_w, wcnt, pk, pw, hsz, hoff, scratch;
     size_t bincnt, binoff, slA, slB, mpre, hub_act, hpart, pcnt, poff;
 };
 
@@ -48,7 +48,6 @@ Layout make_layout(int32_t n, int64_t nnz, int sb)
     const size_t n1 = (size_t)n + 1;
     const size_t z = (size_t)(nnz > 0 ? nnz : 1);
     L.sb = sb;
-    L.slots = 2 * (int64_t)z + (int64_t)z / 64 + 1024;
     L.scratch_elems = scan_scratch_elems((int64_t)n1);
     L.scalars = take(sizeof(DevScalars));
     L.Cp = take(4 * n1);
@@ -79,8 +78,12 @@ Layout make_layout(int32_t n, int64_t nnz, int sb)
     L.tgtB = take(4 * z);
     L.wA = take((size_t)sb * z);
     L.wB = take((size_t)sb * z);
-    L.hkeys = take(4 * (size_t)L.slots);
-    L.hvals = take((size_t)sb * (size_t)L.slots);
+    // hub rows / hub communities: staged communities and partitioned pairs
+    L.hstage = take(4 * z);
+    L.hstage_w = take((size_t)sb * z);
+    L.wcnt = take(4 * ((size_t)z / 1024 + 64));  // per aggregation window (>= 1/4096 entries)
+    L.pk = take(4 * z);
+    L.pw = take((size_t)sb * z);
     L.hsz = take(8 * (n1 + 1));
     L.hoff = take(8 * (n1 + 1));
     L.scratch = take(8 * (size_t)L.scratch_elems);
@@ -158,8 +161,8 @@ struct louvain_ctx {
     void *K, *Sig;
     int32_t *off_buf[2], *deg_buf[2], *tgt_buf[2];
     void *w_buf[2];
-    int32_t *hkeys;
-    void *hvals;
+    int32_t *hstage, *pk, *wcnt;
+    void *pw, *hstage_w;
     int64_t *hsz, *hoff, *scratch;
     int32_t *bincnt, *binoff, *slA, *slB, *mpre;
     void *hpart;
@@ -372,17 +375,12 @@ int move_phase(louvain_ctx *ctx)
     a.mv_d = ctx->mv_d;
     a.spread = &ctx->sc->spread[0][0];
     a.mv_count = &ctx->sc->mv_count;
-    a.hstage = ctx->hkeys;
+    a.hstage = ctx->hstage;
     a.pcount = ctx->pcnt;
     a.pcur = ctx->pcnt + ctx->hub_tslices;  // zeroed together with pcount every round
     a.poff = ctx->poff;
-    {
-        // partitioned hub pairs go to the CSR buffer the next level will be built in,
-        // which is free while this level moves
-        const int nbuf = l.buf == 0 ? 1 : 0;
-        a.pk = ctx->tgt_buf[nbuf];
-        a.pw = (ST *)ctx->w_buf[nbuf];
-    }
+    a.pk = ctx->pk;
+    a.pw = (ST *)ctx->pw;
     a.hoff = ctx->hoff;
     a.hslice = ctx->slA;
     a.htslice = ctx->slB;
@@ -568,14 +566,14 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
     const int hubs = cb.start[NBINS] - cb.start[NBINS - 1];
     int32_t row_slices = 0, table_slices = 0;
     if (hubs > 0) {
-        // member row lengths prefix (windows of hub communities), HBM table
-        // offsets, row slices (in cursor) and table slices (in ccount)
+        // member row lengths prefix (flattened member rows of hub communities),
+        // sorting slices (in cursor) and partitions (in ccount)
         launch_member_degrees(l.n, ctx->members, l.off, l.deg, ctx->cursor, s);
         launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->mpre, l.n, ctx->scratch, nullptr,
                                                 s);
-        launch_hub_sizes(ctx->cbinorder, cb.start[NBINS - 1], cb.start[NBINS], nullptr, ctx->ctot,
-                         nc, ctx->hsz, ctx->cursor, ctx->ccount, s);
-        launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
+        launch_hub_move_sizes(ctx->cbinorder, cb.start[NBINS - 1], cb.start[NBINS], nullptr,
+                              ctx->ctot, (int)sizeof(ST), ctx->hsz, ctx->cursor, ctx->ccount, s,
+                              AGG_PSLICE);
         launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->slA, hubs, ctx->scratch,
                                                 &ctx->sc->hub_slices, s);
         launch_exclusive_scan<int32_t, int32_t>(ctx->ccount, ctx->slB, hubs, ctx->scratch,
@@ -603,9 +601,15 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
     g.ydeg = ydeg;
     g.ytgt = ytgt;
     g.yw = yw;
-    g.hkeys = ctx->hkeys;
-    g.hvals = (ST *)ctx->hvals;
-    g.hoff = ctx->hoff;
+    g.hstage = ctx->hstage;
+    g.hstage_w = (ST *)ctx->hstage_w;
+    g.wcnt = ctx->wcnt;
+    g.pk = ctx->pk;
+    g.pw = (ST *)ctx->pw;
+    g.pcount = ctx->pcnt;
+    g.pcur = ctx->pcnt + table_slices;  // zeroed together with pcount
+    g.poff = ctx->poff;
+    g.tslices = &ctx->sc->hub_tslices;
     g.mpre = ctx->mpre;
     g.cslice = ctx->slA;
     g.tslice = ctx->slB;
@@ -619,7 +623,7 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
         if (b < NBINS - 1)
             launch_aggregate<C>(b, g, block_log2s(cmax[b]), s);
         else
-            launch_aggregate_hub<C>(g, row_slices, table_slices, s);
+            launch_aggregate_hub<C>(g, row_slices, table_slices, ctx->scratch, s);
         CKL();
         TRY(prof_end(ctx, F_AGG0 + b, ev));
     }
@@ -880,8 +884,11 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     ctx->tgt_buf[1] = (int32_t *)(b + L.tgtB);
     ctx->w_buf[0] = b + L.wA;
     ctx->w_buf[1] = b + L.wB;
-    ctx->hkeys = (int32_t *)(b + L.hkeys);
-    ctx->hvals = b + L.hvals;
+    ctx->hstage = (int32_t *)(b + L.hstage);
+    ctx->hstage_w = b + L.hstage_w;
+    ctx->wcnt = (int32_t *)(b + L.wcnt);
+    ctx->pk = (int32_t *)(b + L.pk);
+    ctx->pw = b + L.pw;
     ctx->hsz = (int64_t *)(b + L.hsz);
     ctx->hoff = (int64_t *)(b + L.hoff);
     ctx->scratch = (int64_t *)(b + L.scratch);
@@ -895,7 +902,6 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     ctx->mpre = (int32_t *)(b + L.mpre);
     ctx->hub_act = b + L.hub_act;
     // the scalar block keeps W; the hash slab starts empty and every user clears what it used
-    launch_init_hash_slab(ctx->hkeys, ctx->hvals, L.slots, L.sb, ctx->s);
     launch_iota(ctx->top, n, ctx->s);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->s) != hipSuccess) {
         g_last_hip_error = "workspace initialisation failed";

@@ -133,6 +133,31 @@ def test_det_hub_bins():
     det_parity(hub_graph())
 
 
+def big_star(leaves):
+    """A centre joined to `leaves` leaves that are also joined in pairs (2k+1, 2k+2).
+    Its row of 4M distinct communities overfills the LDS table of every hub partition
+    in the first iteration, so the range-splitting passes run."""
+    assert leaves % 2 == 0
+    n = leaves + 1
+    deg = np.full(n, 2, dtype=np.int64)
+    deg[0] = leaves
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum(deg)
+    tgt = np.empty(off[-1], dtype=np.int32)
+    tgt[:leaves] = np.arange(1, n, dtype=np.int32)
+    leaf = np.arange(1, n, dtype=np.int64)
+    partner = np.where(leaf % 2 == 1, leaf + 1, leaf - 1)
+    rows = tgt[leaves:].reshape(leaves, 2)
+    rows[:, 0] = 0
+    rows[:, 1] = partner
+    return graphgen.CSR(n=n, offsets=off, targets=tgt, weights=np.ones(off[-1], dtype=np.int32),
+                        name="star%d" % leaves)
+
+
+def test_det_hub_partition_overflow():
+    det_parity(big_star(4_000_000), max_passes=2)
+
+
 def test_det_edge_cases():
     for csr in [graphgen.from_edges(0, [], name="empty"), graphgen.from_edges(1, [], name="one"),
                 graphgen.from_edges(7, [], name="isolated"),
