@@ -24,6 +24,7 @@ calls for, as seeded synthetic stand-ins (no dataset is read):
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import re
 import subprocess
@@ -169,6 +170,65 @@ def cliques(k: int, s: int, bridges: Sequence[Tuple[int, int]] = (), name: str =
     edges = [(q * s + i, q * s + j) for q in range(k) for i in range(s) for j in range(i + 1, s)]
     edges += list(bridges)
     return from_edges(k * s, edges, name=name or "cliques%dx%d" % (k, s))
+
+
+def union(graphs: Sequence[CSR], name: str = "") -> Tuple[CSR, np.ndarray]:
+    """Disjoint union of CSRs (graph g's vertices shifted by the vertices before
+    it) and the graph offsets int32[G+1] that mark each graph's vertex range."""
+    sizes = np.array([g.n for g in graphs], dtype=np.int64)
+    go = np.zeros(len(graphs) + 1, dtype=np.int64)
+    go[1:] = np.cumsum(sizes)
+    if go[-1] >= 2 ** 31:
+        raise ValueError("union too large for int32 vertex ids")
+    nnz = np.array([g.nnz for g in graphs], dtype=np.int64)
+    eo = np.zeros(len(graphs) + 1, dtype=np.int64)
+    eo[1:] = np.cumsum(nnz)
+    off = np.zeros(int(go[-1]) + 1, dtype=np.int64)
+    tgt = np.empty(int(eo[-1]), dtype=np.int32)
+    w = np.empty(int(eo[-1]), dtype=np.int32)
+    for i, g in enumerate(graphs):
+        off[go[i]:go[i + 1] + 1] = g.offsets + eo[i]
+        tgt[eo[i]:eo[i + 1]] = g.targets[:g.nnz] + np.int32(go[i])
+        w[eo[i]:eo[i + 1]] = g.weights[:g.nnz]
+    return CSR(int(go[-1]), off, tgt, w, name or "union%d" % len(graphs)), go.astype(np.int32)
+
+
+def batch_sbm_specs(count: int, seed: int = 4, n_min: int = 200, n_max: int = 50_000,
+                    ratio: float = 0.02, k_cap: int = 200):
+    """Parameters of `count` planted-partition SBMs of uneven size: n log-uniform
+    in [n_min, n_max], mean degree uniform in [8, 40], k uniform in 4..k_max
+    (the largest k <= k_cap whose p_in stays <= 1), p_out = ratio * p_in.
+    Graph g draws from SplitMix64 under key (seed << 32) | g."""
+    specs = []
+    for g in range(count):
+        key = ((int(seed) << 32) | g) & ((1 << 64) - 1)
+        u = [splitmix_draw(key, c) / 2.0 ** 64 for c in range(3)]
+        n = int(round(math.exp(math.log(n_min) + u[0] * (math.log(n_max) - math.log(n_min)))))
+        dbar = 8.0 + 32.0 * u[1]
+
+        def p_in_of(k):
+            s = n / k
+            return dbar / ((s - 1.0) + ratio * (n - s))
+
+        k_max = 4
+        for k in range(4, k_cap + 1):
+            if p_in_of(k) <= 1.0:
+                k_max = k
+        k = 4 + int(u[2] * (k_max - 3))
+        k = min(k, k_max)
+        p_in = p_in_of(k)
+        specs.append({"n": n, "k": k, "p_in": p_in, "p_out": ratio * p_in,
+                      "seed": (key + 1) & ((1 << 64) - 1)})
+    return specs
+
+
+def batch_sbm(count: int, seed: int = 4, threads: int = 0, **kw) -> Tuple[CSR, np.ndarray, list]:
+    """The union of `count` SBMs from batch_sbm_specs, its graph offsets and the specs."""
+    specs = batch_sbm_specs(count, seed, **kw)
+    graphs = [sbm(sp["n"], sp["k"], sp["p_in"], sp["p_out"], seed=sp["seed"], threads=threads)
+              for sp in specs]
+    u, go = union(graphs, name="batch%d" % count)
+    return u, go, specs
 
 
 _RMAT = re.compile(r"^rmat(\d+)-(\d+)$")

@@ -224,6 +224,47 @@ int louvain_get_stats(louvain_ctx *ctx, louvain_stats *stats);
 int louvain_kernel_stats(louvain_ctx *ctx, louvain_kernel_stat *out, int32_t max,
                          int32_t *count);
 
+/*
+ * Batches: several independent graphs run through one launch sequence as
+ * the union of their CSRs (graph g owns the vertices [graph_offsets[g],
+ * graph_offsets[g+1]) and only edges among them).  Every graph keeps its
+ * own method: scores use its own W (Eq. 2), its own local-moving test
+ * (Alg. 2: delta-Q <= tau) and its own pass-loop stops (Alg. 1: converged in
+ * one sweep, or too few merges), and the deterministic rounds number its
+ * vertices from 0, so each graph's membership is the one louvain_run gives
+ * for that graph alone (bit for bit in deterministic mode).  The batch
+ * stops when every graph has.
+ */
+
+/* Device bytes for a batch of `graphs` graphs with n vertices and nnz entries in total. */
+int louvain_batch_workspace_size(int32_t graphs, int32_t n, int64_t nnz, int64_t total_weight,
+                                 const louvain_params *p, size_t *bytes);
+
+/*
+ * As louvain_init for the union graph, plus graph_offsets: int32[graphs+1]
+ * (device or host memory, read once), 0 = graph_offsets[0] <= ... <=
+ * graph_offsets[graphs] = n; empty graphs are allowed.  Afterwards the
+ * usual louvain_move / louvain_aggregate / louvain_run / louvain_reset
+ * calls drive the whole batch.  louvain_run's membership holds dense ids
+ * over the union, each graph's ids contiguous and in the order of its own
+ * (subtract the smallest id in its range to get its own membership); its
+ * modularity is that of the union graph.
+ * Errors: those of louvain_init, and EINVAL for graphs < 1, malformed
+ * graph_offsets or an entry that leaves its graph.
+ */
+int louvain_init_batch(louvain_ctx **ctx, int32_t graphs, const int32_t *graph_offsets,
+                       int32_t n, int64_t nnz, const int32_t *offsets, const int32_t *targets,
+                       const int32_t *weights, void *workspace, size_t workspace_bytes,
+                       const louvain_params *p, void *stream);
+
+/*
+ * After louvain_run of a batch: per graph its modularity (Eq. 1 with its own
+ * W; 0 for an edgeless graph) and its number of communities, into host
+ * arrays of `graphs` entries (either may be NULL).
+ * Errors: EINVAL (NULL ctx or not a batch), ESTATE (before louvain_run), EHIP.
+ */
+int louvain_batch_results(louvain_ctx *ctx, double *modularity, int32_t *communities);
+
 /* Release host-side state (the caller's device buffers are untouched). NULL is a no-op. */
 void louvain_destroy(louvain_ctx *ctx);
 

@@ -27,6 +27,7 @@ EXPORTS = (
     "louvain_aggregate", "louvain_run", "louvain_membership", "louvain_level_labels",
     "louvain_level_graph", "louvain_move_trace", "louvain_reset", "louvain_total_weight",
     "louvain_get_stats", "louvain_kernel_stats", "louvain_destroy", "louvain_strerror",
+    "louvain_batch_workspace_size", "louvain_init_batch", "louvain_batch_results",
 )
 
 
@@ -113,6 +114,13 @@ def load_library():
     lib.louvain_get_stats.argtypes = [vp, P(CStats)]
     lib.louvain_kernel_stats.restype = ctypes.c_int
     lib.louvain_kernel_stats.argtypes = [vp, P(CKernelStat), i32, P(i32)]
+    lib.louvain_batch_workspace_size.restype = ctypes.c_int
+    lib.louvain_batch_workspace_size.argtypes = [i32, i32, i64, i64, P(CParams), P(ctypes.c_size_t)]
+    lib.louvain_init_batch.restype = ctypes.c_int
+    lib.louvain_init_batch.argtypes = [P(vp), i32, vp, i32, i64, vp, vp, vp, vp, ctypes.c_size_t,
+                                       P(CParams), vp]
+    lib.louvain_batch_results.restype = ctypes.c_int
+    lib.louvain_batch_results.argtypes = [vp, vp, vp]
     lib.louvain_destroy.restype = None
     lib.louvain_destroy.argtypes = [vp]
     lib.louvain_strerror.restype = ctypes.c_char_p
@@ -156,15 +164,30 @@ def workspace_bytes(n: int, nnz: int, total_weight: int = -1, params: Optional[C
     return int(out.value)
 
 
+def batch_workspace_bytes(graphs: int, n: int, nnz: int, total_weight: int = -1,
+                          params: Optional[CParams] = None) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().louvain_batch_workspace_size(int(graphs), int(n), int(nnz),
+                                                       int(total_weight),
+                                                       ctypes.byref(params) if params else None,
+                                                       ctypes.byref(out)),
+           "louvain_batch_workspace_size")
+    return int(out.value)
+
+
 class Louvain:
-    """One graph resident on the GPU and its Louvain context.
+    """One graph (or a batch of independent graphs) resident on the GPU and its
+    Louvain context.
 
     offsets, targets, weights: int32 CUDA tensors (CSR of a symmetric graph).
+    graph_offsets (optional, int32 of G+1 entries, host or device): the CSR is
+    the union of G independent graphs, graph g owning vertices
+    [graph_offsets[g], graph_offsets[g+1]); each is run as if alone.
     The workspace is allocated here with torch; kernels run on ``stream`` (a
     torch.cuda.Stream, default: the current stream).
     """
 
-    def __init__(self, offsets, targets, weights, stream=None, **params):
+    def __init__(self, offsets, targets, weights, stream=None, graph_offsets=None, **params):
         import torch
         self._torch = torch
         lib = load_library()
@@ -180,16 +203,31 @@ class Louvain:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = make_params(**params)
         W = int(weights.sum(dtype=torch.int64).item()) if self.nnz else 0
-        nbytes = workspace_bytes(self.n, self.nnz, W, self.params)
+        self.graphs = None
+        if graph_offsets is not None:
+            go = torch.as_tensor(graph_offsets, dtype=torch.int32).to(self.device).contiguous()
+            self.graphs = int(go.numel()) - 1
+            self.graph_offsets = go
+            nbytes = batch_workspace_bytes(self.graphs, self.n, self.nnz, W, self.params)
+        else:
+            nbytes = workspace_bytes(self.n, self.nnz, W, self.params)
         self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
         self._ctx = ctypes.c_void_p(None)
         dummy = self.workspace.data_ptr()
-        rc = lib.louvain_init(ctypes.byref(self._ctx), self.n, self.nnz, offsets.data_ptr(),
-                              targets.data_ptr() if self.nnz else dummy,
-                              weights.data_ptr() if self.nnz else dummy,
-                              self.workspace.data_ptr(), nbytes, ctypes.byref(self.params),
-                              ctypes.c_void_p(self.stream.cuda_stream))
-        _check(rc, "louvain_init")
+        tp = targets.data_ptr() if self.nnz else dummy
+        wp = weights.data_ptr() if self.nnz else dummy
+        sp = ctypes.c_void_p(self.stream.cuda_stream)
+        if self.graphs is None:
+            rc = lib.louvain_init(ctypes.byref(self._ctx), self.n, self.nnz, offsets.data_ptr(), tp,
+                                  wp, self.workspace.data_ptr(), nbytes, ctypes.byref(self.params),
+                                  sp)
+            _check(rc, "louvain_init")
+        else:
+            rc = lib.louvain_init_batch(ctypes.byref(self._ctx), self.graphs, go.data_ptr(), self.n,
+                                        self.nnz, offsets.data_ptr(), tp, wp,
+                                        self.workspace.data_ptr(), nbytes,
+                                        ctypes.byref(self.params), sp)
+            _check(rc, "louvain_init_batch")
 
     # -- lifecycle
     def close(self):
@@ -229,6 +267,26 @@ class Louvain:
         _check(load_library().louvain_run(self._ctx, membership.data_ptr(), ctypes.byref(q),
                                           ctypes.byref(st)), "louvain_run")
         return membership[:self.n], float(q.value), st.as_dict()
+
+    def batch_results(self):
+        """After run() of a batch: (per-graph modularity list, per-graph community counts)."""
+        import numpy as np
+        q = np.zeros(self.graphs, dtype=np.float64)
+        c = np.zeros(self.graphs, dtype=np.int32)
+        _check(load_library().louvain_batch_results(self._ctx, q.ctypes.data, c.ctypes.data),
+               "louvain_batch_results")
+        return q.tolist(), c.tolist()
+
+    def split_membership(self, membership):
+        """Per-graph memberships (host numpy arrays, ids from 0) of a batch's union membership."""
+        import numpy as np
+        m = membership.cpu().numpy() if hasattr(membership, "cpu") else np.asarray(membership)
+        go = self.graph_offsets.cpu().numpy()
+        out = []
+        for g in range(self.graphs):
+            part = m[go[g]:go[g + 1]]
+            out.append(part - part.min() if part.size else part.copy())
+        return out
 
     def membership(self):
         out = self._torch.empty(max(self.n, 1), dtype=self._torch.int32, device=self.device)

@@ -125,7 +125,7 @@ struct DevScalars {
     int32_t bin_start[8];   // bin boundaries of the binning step (NBINS + 1 used)
     int32_t bin_maxlen[8];  // longest row per bin (binning step)
     int32_t mv_count;       // deferred moves of the current round (deterministic mode)
-    int32_t pad0;
+    int32_t running;        // batches: graphs still moving after this iteration (then reset)
     // --- fields above are cleared at the start of every local-moving phase ---
     int32_t err;            // validation: bit 0 offsets, 1 targets, 2 weights
     int32_t pad1;
@@ -135,6 +135,8 @@ struct DevScalars {
     unsigned long long W;
     unsigned long long sigma;       // sum of intra-community entries
     unsigned long long s2[2];       // 128-bit sum of Sigma_c^2
+    int32_t alive;                  // batches: graphs not stopped after the last aggregation test
+    int32_t pad2;
     unsigned long long work[16][5]; // algorithmic work counters per kernel family
     int32_t pad[16];
     // --- per-wavefront counter rows (folded and cleared by the iteration end);
@@ -147,6 +149,21 @@ struct DevScalars {
 // NBINS..2*NBINS-1 [communities, members, entries, emitted, -].
 constexpr int WORK_MOVE = 0;
 constexpr int WORK_AGG = NBINS;
+
+// A batch of independent graphs run as one union graph: graph g owns the
+// vertex range [gvb[g], gvb[g+1]) of every level and is scored, tested for
+// convergence and stopped on its own (its own W, gain sum and iteration
+// count), so each graph's result is the one it would have alone.  All
+// pointers are null for a single graph.
+struct BatchArgs {
+    const int32_t *gid;        // graph of each vertex of the level
+    const int32_t *gvb;        // first vertex of each graph at this level (G + 1)
+    const int64_t *gW;         // total weight (2m) per graph
+    unsigned long long *gsum;  // 128-bit gain sum per graph, this iteration
+    int32_t *gst;              // bit 0: converged in this pass, bit 1: stopped
+    int32_t *giter;            // iterations run in this pass
+    int32_t G;
+};
 
 // ---------------------------------------------------------------------------
 // Device helpers.

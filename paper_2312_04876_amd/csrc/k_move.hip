@@ -45,6 +45,21 @@ __device__ inline int lds_insert(int32_t *keys, ST *vals, int log2s, int32_t c, 
     }
 }
 
+// W (2m) of vertex v's graph: the level's W, or in a batch its own graph's.
+template <class C>
+__device__ inline int64_t vertex_W(const MoveArgs<C> &a, int v)
+{
+    return a.bt.gid ? a.bt.gW[a.bt.gid[v]] : a.W;
+}
+
+// A batch adds each mover's gain to its graph's sum (the per-graph
+// convergence test); a single graph only uses the per-wavefront counters.
+template <class C>
+__device__ inline void graph_gain(const MoveArgs<C> &a, int v, typename C::SC gain)
+{
+    if (a.bt.gid) atomic_add_i128(a.bt.gsum + 2 * a.bt.gid[v], (i128)gain);
+}
+
 // Candidate order: higher score first, then lower community id.
 template <typename SC>
 __device__ inline bool better(SC s, int c, SC bs, int bc)
@@ -56,13 +71,13 @@ __device__ inline bool better(SC s, int c, SC bs, int bc)
 // weight to the own community, non-self entries).  Returns true to move and
 // sets the gain N = best - stay.
 template <class C>
-__device__ inline bool decide(const MoveArgs<C> &a, int dc, typename C::ST kv,
+__device__ inline bool decide(const MoveArgs<C> &a, int64_t W, int dc, typename C::ST kv,
                               typename C::SC best, int bc, typename C::ST hd, int nonself,
                               typename C::SC *gain)
 {
     typedef typename C::SC SC;
     if (nonself <= 0 || bc == INT_MAX) return false;
-    const SC stay = (SC)a.W * (SC)hd - (SC)kv * ((SC)a.Sig[dc] - (SC)kv);
+    const SC stay = (SC)W * (SC)hd - (SC)kv * ((SC)a.Sig[dc] - (SC)kv);
     if (!(best > stay)) return false;
     if (a.rule && a.size[dc] == 1 && a.size[bc] == 1 && bc > dc) return false;
     *gain = best - stay;
@@ -198,7 +213,7 @@ __device__ inline void flush_counters(const MoveArgs<C> &a, typename C::SC gain,
 // Score of one table slot for vertex with label dc and weight kv; updates the
 // running best or the weight to the own community.
 template <class C>
-__device__ inline void consider(const MoveArgs<C> &a, int dc, typename C::ST kv, int k,
+__device__ inline void consider(const MoveArgs<C> &a, int64_t W, int dc, typename C::ST kv, int k,
                                 typename C::ST x, typename C::ST sig, typename C::SC &best,
                                 int &bc, typename C::ST &hd)
 {
@@ -208,7 +223,7 @@ __device__ inline void consider(const MoveArgs<C> &a, int dc, typename C::ST kv,
         hd = x;
         return;
     }
-    const SC sc = (SC)a.W * (SC)x - (SC)kv * (SC)sig;
+    const SC sc = (SC)W * (SC)x - (SC)kv * (SC)sig;
     if (better(sc, k, best, bc)) {
         best = sc;
         bc = k;
@@ -295,11 +310,13 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
         const int v = has ? a.worklist[a.list_begin + idx] : 0;
         int beg = 0, d = 0, dc = -1;
         ST kv = 0;
+        int64_t Wv = a.W;
         if (has) {
             beg = a.off[v];
             d = row_len(a.off, a.deg, v);
             dc = a.Cp[v];
             kv = a.K[v];
+            Wv = vertex_W(a, v);
         }
         int j[E], c[E], slot[E];
         bool own[E];
@@ -339,7 +356,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             if (c[k] == dc) {
                 hd = x[k];
             } else {
-                const SC sc = (SC)a.W * (SC)x[k] - (SC)kv * (SC)sg[k];
+                const SC sc = (SC)Wv * (SC)x[k] - (SC)kv * (SC)sg[k];
                 if (better(sc, c[k], best, bc)) {
                     best = sc;
                     bc = c[k];
@@ -365,7 +382,8 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             nonself += __shfl_xor(nonself, o, 64);
         }
         SC gain = 0;
-        const bool mv = has && decide<C>(a, dc, kv, best, bc, hd, nonself, &gain);
+        const bool mv = has && decide<C>(a, Wv, dc, kv, best, bc, hd, nonself, &gain);
+        if (mv && gl == 0) graph_gain<C>(a, v, gain);
         if (has && gl == 0) {
             ++nv;
             if (mv) {
@@ -469,6 +487,7 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
         const int d = row_len(a.off, a.deg, v);
         const int dc = a.Cp[v];
         const ST kv = a.K[v];
+        const int64_t Wv = vertex_W(a, v);
         const int log2s = block_log2s(d);
         int nonself = 0;
         for (int e0 = threadIdx.x; e0 < d; e0 += 4 * BT) {
@@ -509,12 +528,13 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
 #pragma unroll
             for (int q = 0; q < 4; ++q) sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+            for (int q = 0; q < 4; ++q) consider<C>(a, Wv, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
         }
         block_reduce<SC, ST, NW>(r, best, bc, hd, nonself);
         if (threadIdx.x == 0) {
             SC gain = 0;
-            const bool mv = decide<C>(a, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0], &gain);
+            const bool mv = decide<C>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0], &gain);
+            if (mv) graph_gain<C>(a, v, gain);
             r.move = mv ? 1 : 0;
             ++nv;
             if (mv) {
@@ -660,6 +680,7 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
     const int v = a.binorder[a.list_begin + h];
     const int dc = a.Cp[v];
     const ST kv = a.K[v];
+    const int64_t Wv = vertex_W(a, v);
     const int pb = a.poff[gp], pn = a.pcount[gp];
     // table of 2^lg slots: twice the pairs (so no overflow) when that fits
     int lg = 8;
@@ -734,7 +755,7 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
 #pragma unroll
             for (int q = 0; q < 4; ++q) sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) consider<C>(a, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+            for (int q = 0; q < 4; ++q) consider<C>(a, Wv, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
         }
     }
     block_reduce<SC, ST, 4>(r, best, bc, hd, nk);
@@ -771,6 +792,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
         const int q1 = h + 1 < a.nhubs ? a.htslice[h + 1] : (int)*a.htslices;
         const int dc = a.Cp[v];
         const ST kv = a.K[v];
+        const int64_t Wv = vertex_W(a, v);
         SC best = score_min<SC>();
         int bc = INT_MAX;
         ST hd = 0;
@@ -791,7 +813,8 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
             // a hub row holds more than the LDS row limit of distinct targets, so
             // it always has an entry other than a self-loop
             SC gain = 0;
-            const bool mv = decide<C>(a, dc, kv, r.best[0], r.bc[0], r.hd[0], 1, &gain);
+            const bool mv = decide<C>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], 1, &gain);
+            if (mv) graph_gain<C>(a, v, gain);
             r.move = mv ? 1 : 0;
             ++nv;
             if (mv) {

@@ -394,8 +394,14 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a)
         if (p < a.nb) {
             const int v = a.binorder[p];
             bool act = a.prune ? (a.flags[v] != 0) : true;
+            int lv = v;  // index within its graph (a batch numbers each graph from 0)
+            if (a.bt.gid) {
+                const int g = a.bt.gid[v];
+                if (a.bt.gst[g]) act = false;
+                lv = v - a.bt.gvb[g];
+            }
             if (act && a.round_bits > 0)
-                act = round_of(a.seed, a.round_bits, a.pass, a.it, v) == a.round;
+                act = round_of(a.seed, a.round_bits, a.pass, a.it, lv) == a.round;
             if (act) {
                 if (a.prune) a.flags[v] = 0;
                 b = 0;
@@ -510,7 +516,7 @@ __global__ void k_round_end(DevScalars *sc, int it)
     if (t == 0) sc->mv_count = 0;
 }
 
-__global__ __launch_bounds__(64) void k_iter_end(DevScalars *sc, int it, double tau)
+__global__ __launch_bounds__(64) void k_iter_end(DevScalars *sc, int it, double tau, int batch)
 {
     if (sc->done) return;
     const int lane = threadIdx.x;  // one counter row per lane
@@ -534,7 +540,149 @@ __global__ __launch_bounds__(64) void k_iter_end(DevScalars *sc, int it, double 
     const double dq = iteration_dq(g, sc->W);
     sc->dq[it] = dq;
     sc->iters = it + 1;
-    if (dq <= tau) sc->done = 1;
+    if (batch) {
+        // a batch stops when every graph has converged (or stopped)
+        if (sc->running == 0) sc->done = 1;
+        sc->running = 0;
+    } else if (dq <= tau) {
+        sc->done = 1;
+    }
+}
+
+// ---- batches of independent graphs (see BatchArgs)
+
+// gid[v] = graph owning vertex v (the last graph whose first vertex is <= v,
+// so empty graphs own nothing).
+__global__ void k_batch_gid(int32_t n, const int32_t *gvb, int32_t G, int32_t *gid)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        gid[v] = owner_slice(gvb, G, (int)v);
+}
+
+// Checks the graph offsets' shape and that every entry stays inside its
+// graph (err bit 3), and adds every row's weight to its graph's W.
+__global__ void k_batch_check(int32_t n, const int32_t *off, const int32_t *tgt, const int32_t *w,
+                              const int32_t *gid, const int32_t *gvb, int64_t *gW, int32_t *err)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int g = gid[v];
+        const int lo = gvb[g], hi = gvb[g + 1];
+        int64_t sum = 0;
+        bool bad = false;
+        for (int e = off[v]; e < off[v + 1]; ++e) {
+            const int j = tgt[e];
+            bad |= j < lo || j >= hi;
+            sum += w[e];
+        }
+        if (bad) atomicOr(err, 8);
+        if (sum) atomicAdd((unsigned long long *)&gW[g], (unsigned long long)sum);
+    }
+}
+
+// Start of a run: every graph alive, each its own vertices as communities.
+__global__ void k_batch_reset(BatchArgs b, int32_t *gcomm)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < b.G; g += gridDim.x * blockDim.x) {
+        b.gst[g] = 0;
+        b.giter[g] = 0;
+        gcomm[g] = b.gvb[g + 1] - b.gvb[g];
+    }
+}
+
+// Start of a local-moving phase: no graph has converged in it yet.
+__global__ void k_batch_pass_begin(BatchArgs b)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < b.G; g += gridDim.x * blockDim.x) {
+        b.gst[g] &= 2;
+        b.giter[g] = 0;
+        b.gsum[2 * g] = 0;
+        b.gsum[2 * g + 1] = 0;
+    }
+}
+
+// End of an iteration, per graph still moving: one more iteration, then its
+// own delta-Q test; counts the graphs that keep moving in sc->running.
+__global__ void k_batch_iter_end(BatchArgs b, DevScalars *sc, double tau)
+{
+    if (sc->done) return;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < b.G; g += gridDim.x * blockDim.x) {
+        if (b.gst[g]) continue;
+        b.giter[g] += 1;
+        const double dq = iteration_dq(join_i128(b.gsum[2 * g], b.gsum[2 * g + 1]),
+                                       (unsigned long long)b.gW[g]);
+        b.gsum[2 * g] = 0;
+        b.gsum[2 * g + 1] = 0;
+        if (dq <= tau)
+            b.gst[g] |= 1;
+        else
+            atomicAdd(&sc->running, 1);
+    }
+}
+
+// After local moving and the community count of a level (idmap = exclusive
+// scan of the used labels over the level's n vertices, nc in total): each
+// graph's first community and count, and the stop test of Alg. 1 per graph
+// (converged in one sweep, or too few merges); sc->alive counts the graphs
+// that go on.
+__global__ void k_batch_agg_test(BatchArgs b, const int32_t *idmap, int32_t n, int32_t nc,
+                                 double aggtol, int32_t *gvb_next, int32_t *gcomm, DevScalars *sc)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < b.G; g += gridDim.x * blockDim.x) {
+        const int v0 = b.gvb[g], v1 = b.gvb[g + 1];
+        const int c0 = v0 < n ? idmap[v0] : nc, c1 = v1 < n ? idmap[v1] : nc;
+        gvb_next[g] = c0;
+        if (g == b.G - 1) gvb_next[b.G] = nc;
+        gcomm[g] = c1 - c0;
+        if (b.gst[g] & 2) continue;
+        if (b.giter[g] <= 1 || (double)(c1 - c0) / (double)(v1 - v0) > aggtol)
+            b.gst[g] |= 2;
+        else
+            atomicAdd(&sc->alive, 1);
+    }
+}
+
+// Graph of every super-vertex of the next level (labels already dense).
+__global__ void k_batch_gid_next(int32_t n, const int32_t *labels, const int32_t *gid,
+                                 int32_t *gid_next)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        gid_next[labels[v]] = gid[v];
+}
+
+// Per-graph modularity terms on a level with labels: sigma_g (entries inside
+// a community, one wavefront per row) and S2_g (sum of squared community
+// weights, 128-bit).
+template <typename WT>
+__global__ __launch_bounds__(256) void k_batch_sigma(int32_t n, const int32_t *off,
+                                                     const int32_t *deg, const int32_t *tgt,
+                                                     const WT *w, const int32_t *labels,
+                                                     const int32_t *gid, unsigned long long *gsig)
+{
+    const int lane = threadIdx.x & 63;
+    for (int64_t v = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; v < n;
+         v += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+        const int beg = off[v];
+        const int len = deg ? deg[v] : off[v + 1] - off[v];
+        const int lv = labels[v];
+        unsigned long long sum = 0;
+        for (int e = lane; e < len; e += 64)
+            if (labels[tgt[beg + e]] == lv) sum += (unsigned long long)w[beg + e];
+        sum = wave_sum_u64(sum);
+        if (lane == 0 && sum) atomicAdd(&gsig[gid[v]], sum);
+    }
+}
+
+template <typename ST>
+__global__ void k_batch_s2(int32_t n, const ST *Sig, const int32_t *gid, unsigned long long *gs2)
+{
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const ST x = Sig[c];
+        if (x) atomic_add_i128(gs2 + 2 * gid[c], (i128)x * (i128)x);
+    }
 }
 
 __global__ void k_mark_used(int32_t n, const int32_t *labels, int32_t *used)
@@ -807,10 +955,74 @@ void launch_round_end(DevScalars *sc, int it, hipStream_t s)
     k_round_end<<<1, 64, 0, s>>>(sc, it);
 }
 
-void launch_iter_end(DevScalars *sc, int it, double tau, hipStream_t s)
+void launch_iter_end(DevScalars *sc, int it, double tau, hipStream_t s, const BatchArgs *b)
 {
-    k_iter_end<<<1, 64, 0, s>>>(sc, it, tau);
+    if (b && b->gid) k_batch_iter_end<<<grid_for(b->G, 256), 256, 0, s>>>(*b, sc, tau);
+    k_iter_end<<<1, 64, 0, s>>>(sc, it, tau, b && b->gid ? 1 : 0);
 }
+
+void launch_batch_gid(int32_t n, const int32_t *gvb, int32_t G, int32_t *gid, hipStream_t s)
+{
+    if (n > 0) k_batch_gid<<<grid_for(n, 256), 256, 0, s>>>(n, gvb, G, gid);
+}
+
+void launch_batch_check(int32_t n, const int32_t *off, const int32_t *tgt, const int32_t *w,
+                        const int32_t *gid, const int32_t *gvb, int64_t *gW, int32_t *err,
+                        hipStream_t s)
+{
+    if (n > 0) k_batch_check<<<grid_for(n, 256), 256, 0, s>>>(n, off, tgt, w, gid, gvb, gW, err);
+}
+
+void launch_batch_reset(const BatchArgs &b, int32_t *gcomm, hipStream_t s)
+{
+    if (b.G > 0) k_batch_reset<<<grid_for(b.G, 256), 256, 0, s>>>(b, gcomm);
+}
+
+void launch_batch_pass_begin(const BatchArgs &b, hipStream_t s)
+{
+    if (b.G > 0) k_batch_pass_begin<<<grid_for(b.G, 256), 256, 0, s>>>(b);
+}
+
+void launch_batch_agg_test(const BatchArgs &b, const int32_t *idmap, int32_t n, int32_t nc,
+                           double aggtol, int32_t *gvb_next, int32_t *gcomm, DevScalars *sc,
+                           hipStream_t s)
+{
+    if (b.G > 0)
+        k_batch_agg_test<<<grid_for(b.G, 256), 256, 0, s>>>(b, idmap, n, nc, aggtol, gvb_next,
+                                                             gcomm, sc);
+}
+
+void launch_batch_gid_next(int32_t n, const int32_t *labels, const int32_t *gid, int32_t *gid_next,
+                           hipStream_t s)
+{
+    if (n > 0) k_batch_gid_next<<<grid_for(n, 256), 256, 0, s>>>(n, labels, gid, gid_next);
+}
+
+template <typename WT, typename ST>
+void launch_batch_modularity(int32_t n, const int32_t *off, const int32_t *deg, const int32_t *tgt,
+                             const WT *w, const int32_t *labels, const ST *Sig, const int32_t *gid,
+                             unsigned long long *gsig, unsigned long long *gs2, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_batch_sigma<WT><<<grid_for((int64_t)n * 64, 256), 256, 0, s>>>(n, off, deg, tgt, w, labels,
+                                                                     gid, gsig);
+    k_batch_s2<ST><<<grid_for(n, 256), 256, 0, s>>>(n, Sig, gid, gs2);
+}
+template void launch_batch_modularity<int32_t, int32_t>(int32_t, const int32_t *, const int32_t *,
+                                                        const int32_t *, const int32_t *,
+                                                        const int32_t *, const int32_t *,
+                                                        const int32_t *, unsigned long long *,
+                                                        unsigned long long *, hipStream_t);
+template void launch_batch_modularity<int32_t, int64_t>(int32_t, const int32_t *, const int32_t *,
+                                                        const int32_t *, const int32_t *,
+                                                        const int32_t *, const int64_t *,
+                                                        const int32_t *, unsigned long long *,
+                                                        unsigned long long *, hipStream_t);
+template void launch_batch_modularity<int64_t, int64_t>(int32_t, const int32_t *, const int32_t *,
+                                                        const int32_t *, const int64_t *,
+                                                        const int32_t *, const int64_t *,
+                                                        const int32_t *, unsigned long long *,
+                                                        unsigned long long *, hipStream_t);
 
 void launch_mark_used(int32_t n, const int32_t *labels, int32_t *used, hipStream_t s)
 {

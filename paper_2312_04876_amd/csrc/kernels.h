@@ -90,6 +90,7 @@ struct CompactArgs {
     int32_t *counts;    // per-bin count of this round (zero on entry)
     uint8_t *hub_act;   // per hub (position - bins.start[NBINS-1]): queued this round
     const int32_t *done;
+    BatchArgs bt;       // batches: skip graphs that converged or stopped; rounds by local index
 };
 void launch_compact(const CompactArgs &a, hipStream_t s);
 
@@ -133,6 +134,7 @@ struct MoveArgs {
     const int32_t *done;
     int64_t W;
     int32_t rule;                      // min-label rule for singleton moves
+    BatchArgs bt;                      // batches: per-graph W and gain sums
 };
 // Bins 0-4; grid: workgroups to launch for this bin (each loops over the device count);
 // log2s_max: LDS table size of bin 4 (block_log2s of the bin's longest row).
@@ -162,7 +164,33 @@ void launch_round_end(DevScalars *sc, int it, hipStream_t s);
 // End of an iteration: folds the per-wavefront counter rows into the
 // iteration's gain sum, moves, scanned entries and the work counters, clears
 // them, then the delta-Q test against tau and the done / iters update.
-void launch_iter_end(DevScalars *sc, int it, double tau, hipStream_t s);
+void launch_iter_end(DevScalars *sc, int it, double tau, hipStream_t s,
+                     const BatchArgs *b = nullptr);
+
+// ----------------------------------------------------------------- batches
+// gid[v] for a level whose graph g owns vertices [gvb[g], gvb[g+1]).
+void launch_batch_gid(int32_t n, const int32_t *gvb, int32_t G, int32_t *gid, hipStream_t s);
+// Input check (err bit 3: an entry leaves its graph) and per-graph W (zero on entry).
+void launch_batch_check(int32_t n, const int32_t *off, const int32_t *tgt, const int32_t *w,
+                        const int32_t *gid, const int32_t *gvb, int64_t *gW, int32_t *err,
+                        hipStream_t s);
+// Start of a run: all graphs alive, gcomm[g] = vertices of graph g.
+void launch_batch_reset(const BatchArgs &b, int32_t *gcomm, hipStream_t s);
+// Start of a local-moving phase: converged bits, iteration counts and gain sums cleared.
+void launch_batch_pass_begin(const BatchArgs &b, hipStream_t s);
+// Per-graph community bases (gvb_next), counts (gcomm) and stop test; sc->alive (zero on
+// entry) counts the graphs that go on.
+void launch_batch_agg_test(const BatchArgs &b, const int32_t *idmap, int32_t n, int32_t nc,
+                           double aggtol, int32_t *gvb_next, int32_t *gcomm, DevScalars *sc,
+                           hipStream_t s);
+// gid of the next level from the dense labels.
+void launch_batch_gid_next(int32_t n, const int32_t *labels, const int32_t *gid, int32_t *gid_next,
+                           hipStream_t s);
+// Per-graph sigma and S2 (both zero on entry) of a level with labels.
+template <typename WT, typename ST>
+void launch_batch_modularity(int32_t n, const int32_t *off, const int32_t *deg, const int32_t *tgt,
+                             const WT *w, const int32_t *labels, const ST *Sig, const int32_t *gid,
+                             unsigned long long *gsig, unsigned long long *gs2, hipStream_t s);
 
 // ----------------------------------------------------------------- aggregation
 void launch_mark_used(int32_t n, const int32_t *labels, int32_t *used, hipStream_t s);

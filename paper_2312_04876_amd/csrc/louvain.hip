@@ -33,9 +33,10 @@ struct Layout {
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hstage, hstage_w, wcnt, pk, pw, hsz, hoff, scratch;
     size_t bincnt, binoff, slA, slB, mpre, hub_act, hpart, pcnt, poff;
+    size_t gid[3], gvb[3], gW, gsum, gst, giter, gcomm, gsig, gs2;  // batches
 };
 
-Layout make_layout(int32_t n, int64_t nnz, int sb)
+Layout make_layout(int32_t n, int64_t nnz, int sb, int32_t G = 0)
 {
     Layout L;
     memset(&L, 0, sizeof(L));
@@ -94,6 +95,22 @@ Layout make_layout(int32_t n, int64_t nnz, int sb)
     L.slB = take(4 * (n1 + 1));
     L.mpre = take(4 * (n1 + 1));
     L.hub_act = take(n1);
+    if (G > 0) {
+        // batches: graph of each vertex and first vertex of each graph, for the
+        // input level (0) and two ping-ponged aggregated levels
+        const size_t g1 = (size_t)G + 1;
+        for (int k = 0; k < 3; ++k) {
+            L.gid[k] = take(4 * n1);
+            L.gvb[k] = take(4 * g1);
+        }
+        L.gW = take(8 * g1);
+        L.gsum = take(16 * g1);
+        L.gst = take(4 * g1);
+        L.giter = take(4 * g1);
+        L.gcomm = take(4 * g1);
+        L.gsig = take(8 * g1);
+        L.gs2 = take(16 * g1);
+    }
     // per partition of the hub rows (at most one per 2048 entries, plus one per hub)
     const size_t parts = (size_t)z / 512 + 64;
     L.hpart = take(32 * parts);
@@ -168,6 +185,14 @@ struct louvain_ctx {
     void *hpart;
     int32_t *pcnt, *poff;
     uint8_t *hub_act;
+    // batches of independent graphs (G = 0 for a single graph)
+    int32_t G;
+    int32_t *gid[3], *gvb[3];
+    int64_t *gW;
+    unsigned long long *gsum, *gsig, *gs2;
+    int32_t *gst, *giter, *gcomm;
+    int glev;                 // which gid/gvb pair the current level uses (0 = input)
+    std::vector<double> gq;   // per-graph modularity of the finished run
     int32_t hub_slices;  // row slices of the current level's hubs
     int32_t hub_tslices; // partitions of the current level's hub rows
     int64_t W;
@@ -216,6 +241,22 @@ namespace {
     } while (0)
 
 int bins_of(louvain_ctx *ctx, int b) { return ctx->bins.start[b + 1] - ctx->bins.start[b]; }
+
+// Batch arguments of the current level (all null for a single graph).
+BatchArgs batch_args(louvain_ctx *ctx)
+{
+    BatchArgs b;
+    memset(&b, 0, sizeof(b));
+    if (ctx->G <= 0) return b;
+    b.gid = ctx->gid[ctx->glev];
+    b.gvb = ctx->gvb[ctx->glev];
+    b.gW = ctx->gW;
+    b.gsum = ctx->gsum;
+    b.gst = ctx->gst;
+    b.giter = ctx->giter;
+    b.G = ctx->G;
+    return b;
+}
 
 // ---------------------------------------------------------------- profiling
 int prof_begin(louvain_ctx *ctx, hipEvent_t *ev)
@@ -294,6 +335,10 @@ int setup_level(louvain_ctx *ctx)
     CKL();
     launch_fill_bytes_zero(ctx->sc->spread, sizeof(ctx->sc->spread), s);
     CKL();
+    if (ctx->G > 0) {
+        launch_batch_pass_begin(batch_args(ctx), s);
+        CKL();
+    }
     launch_init_vertices(l.n, ctx->Cp, ctx->size, ctx->fa, ctx->fb, ctx->K, ctx->Sig, ctx->L.sb, s);
     launch_bin_count(l.n, l.off, l.deg, ctx->lds_max, ctx->bincnt, ctx->binoff, ctx->scratch,
                      ctx->sc->bin_start, ctx->sc->bin_maxlen, s);
@@ -391,6 +436,7 @@ int move_phase(louvain_ctx *ctx)
     a.done = &ctx->sc->done;
     a.W = ctx->W;
     a.rule = 1;
+    a.bt = batch_args(ctx);
     int grid[NBINS], log2s[NBINS];
     for (int b = 0; b < NBINS; ++b) {
         const int cnt = bins_of(ctx, b);
@@ -421,6 +467,7 @@ int move_phase(louvain_ctx *ctx)
             ca.counts = ctx->sc->bin_count;
             ca.hub_act = ctx->hub_act;
             ca.done = &ctx->sc->done;
+            ca.bt = a.bt;
             hipEvent_t ev;
             TRY(prof_begin(ctx, &ev));
             launch_compact(ca, s);
@@ -453,7 +500,7 @@ int move_phase(louvain_ctx *ctx)
         }
         hipEvent_t ev;
         TRY(prof_begin(ctx, &ev));
-        launch_iter_end(ctx->sc, it, ctx->tau, s);
+        launch_iter_end(ctx->sc, it, ctx->tau, s, &a.bt);
         CKL();
         TRY(prof_end(ctx, F_ITER, ev));
         CK(hipMemcpyAsync(&ctx->pinned_done[it], &ctx->sc->done, sizeof(int32_t),
@@ -529,8 +576,21 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
     const int P = ctx->pass;
     if (P < LOUVAIN_MAX_PASSES) ctx->st.communities[P] = nc;
     if (communities) *communities = nc;
-    // Alg. 1: globally converged, or too few merges
-    if (ctx->iters_last <= 1 || (double)nc / (double)l.n > ctx->p.aggregation_tolerance) {
+    // Alg. 1: globally converged, or too few merges (per graph in a batch, which
+    // stops when every graph has)
+    const int gnext = ctx->glev == 1 ? 2 : 1;
+    bool stopped;
+    if (ctx->G > 0) {
+        launch_fill_bytes_zero(&ctx->sc->alive, sizeof(int32_t), s);
+        launch_batch_agg_test(batch_args(ctx), ctx->idmap, l.n, nc, ctx->p.aggregation_tolerance,
+                              ctx->gvb[gnext], ctx->gcomm, ctx->sc, s);
+        CKL();
+        TRY(read_scalars(ctx));
+        stopped = ctx->hsc->alive == 0;
+    } else {
+        stopped = ctx->iters_last <= 1 || (double)nc / (double)l.n > ctx->p.aggregation_tolerance;
+    }
+    if (stopped) {
         ctx->state = S_STOPPED;
         if (stop) *stop = 1;
         return LOUVAIN_OK;
@@ -542,6 +602,7 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
     // renumber communities (prefix sum over used ids) and look up the dendrogram
     launch_relabel(l.n, ctx->Cp, ctx->idmap, s);
     launch_relabel(ctx->n, ctx->top, ctx->Cp, s);
+    if (ctx->G > 0) launch_batch_gid_next(l.n, ctx->Cp, ctx->gid[ctx->glev], ctx->gid[gnext], s);
     // community-vertex CSR: count, exclusive scan, fill
     launch_fill_i32(ctx->ccount, 0, (int64_t)nc + 1, s);
     launch_fill_i32(ctx->ctot, 0, (int64_t)nc + 1, s);
@@ -641,6 +702,7 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
     nl.buf = nbuf;
     nl.entries = (int64_t)(emitted1 - emitted0);
     ctx->lev = nl;
+    if (ctx->G > 0) ctx->glev = gnext;
     ctx->tau = ctx->tau / ctx->p.tolerance_drop;
     ctx->pass += 1;
     const bool more = ctx->pass < ctx->p.max_passes;
@@ -686,6 +748,28 @@ int modularity_t(louvain_ctx *ctx, double *q)
     const i128 num = sigma * W - s2;
     const i128 den = W * W;
     *q = den == 0 ? 0.0 : i128_to_f64(num) / i128_to_f64(den);
+    if (ctx->G > 0) {
+        // each graph's own Q (its own W) from per-graph sigma and S2
+        const int G = ctx->G;
+        launch_fill_bytes_zero(ctx->gsig, 8 * (int64_t)G, s);
+        launch_fill_bytes_zero(ctx->gs2, 16 * (int64_t)G, s);
+        launch_batch_modularity<typename C::WT, ST>(l.n, l.off, l.deg, l.tgt, lev_w<C>(l), ctx->Cp,
+                                                    (const ST *)ctx->Sig, ctx->gid[ctx->glev],
+                                                    ctx->gsig, ctx->gs2, s);
+        CKL();
+        std::vector<unsigned long long> sig(G), sq(2 * (size_t)G);
+        std::vector<int64_t> gw(G);
+        CK(hipMemcpyAsync(sig.data(), ctx->gsig, 8 * (size_t)G, hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(sq.data(), ctx->gs2, 16 * (size_t)G, hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(gw.data(), ctx->gW, 8 * (size_t)G, hipMemcpyDeviceToHost, s));
+        TRY(sync_stream(ctx));
+        ctx->gq.assign(G, 0.0);
+        for (int g = 0; g < G; ++g) {
+            const i128 Wg = (i128)gw[g];
+            const i128 ng = (i128)sig[g] * Wg - join_i128(sq[2 * g], sq[2 * g + 1]);
+            ctx->gq[g] = Wg == 0 ? 0.0 : i128_to_f64(ng) / i128_to_f64(Wg * Wg);
+        }
+    }
     return LOUVAIN_OK;
 }
 
@@ -745,6 +829,7 @@ void reset_state(louvain_ctx *ctx)
     l.buf = -1;
     l.entries = ctx->nnz;
     ctx->lev = l;
+    ctx->glev = 0;
     memset(&ctx->st, 0, sizeof(ctx->st));
     ctx->tr_sum.clear();
     ctx->tr_moves.clear();
@@ -787,9 +872,13 @@ int louvain_workspace_size(int32_t n, int64_t nnz, int64_t total_weight, const l
     return LOUVAIN_OK;
 }
 
-int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offsets,
-                 const int32_t *targets, const int32_t *weights, void *workspace,
-                 size_t workspace_bytes, const louvain_params *p, void *stream)
+}  // extern "C"
+
+namespace {
+
+int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t n, int64_t nnz,
+             const int32_t *offsets, const int32_t *targets, const int32_t *weights,
+             void *workspace, size_t workspace_bytes, const louvain_params *p, void *stream)
 {
     if (!out) return LOUVAIN_EINVAL;
     *out = nullptr;
@@ -802,7 +891,8 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     else
         louvain_default_params(&prm);
     if (check_params(&prm)) return LOUVAIN_EINVAL;
-    const size_t need4 = make_layout(n, nnz, 4).total;
+    if (G < 0 || (G > 0 && !graph_offsets)) return LOUVAIN_EINVAL;
+    const size_t need4 = make_layout(n, nnz, 4, G).total;
     if (workspace_bytes < need4) return LOUVAIN_ENOSPC;
 
     louvain_ctx *ctx = new (std::nothrow) louvain_ctx();
@@ -816,6 +906,7 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     ctx->in_w = weights;
     ctx->ws = (unsigned char *)workspace;
     ctx->last_err = hipSuccess;
+    ctx->G = G;
     for (int f = 0; f < F_COUNT; ++f) {
         ctx->fam_ms[f] = 0.0;
         ctx->fam_launches[f] = 0;
@@ -834,7 +925,7 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
         return fail(LOUVAIN_EHIP);
     }
     // validation and W with the narrow layout's scalar block (same offset in both layouts)
-    ctx->L = make_layout(n, nnz, 4);
+    ctx->L = make_layout(n, nnz, 4, G);
     ctx->sc = (DevScalars *)(ctx->ws + ctx->L.scalars);
     launch_fill_bytes_zero(ctx->sc, sizeof(DevScalars), ctx->s);
     launch_validate(n, nnz, offsets, targets, weights, &ctx->sc->err, &ctx->sc->W, ctx->s);
@@ -851,7 +942,7 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     ctx->W = (int64_t)W;
     ctx->wide = W >= (1ull << 31);
     ctx->lds_max = ctx->wide ? LDS_MAX_WIDE : LDS_MAX_NARROW;
-    ctx->L = make_layout(n, nnz, ctx->wide ? 8 : 4);
+    ctx->L = make_layout(n, nnz, ctx->wide ? 8 : 4, G);
     if (workspace_bytes < ctx->L.total) return fail(LOUVAIN_ENOSPC);
     const Layout &L = ctx->L;
     unsigned char *b = ctx->ws;
@@ -901,14 +992,111 @@ int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offse
     ctx->poff = (int32_t *)(b + L.poff);
     ctx->mpre = (int32_t *)(b + L.mpre);
     ctx->hub_act = b + L.hub_act;
-    // the scalar block keeps W; the hash slab starts empty and every user clears what it used
+    if (G > 0) {
+        for (int k = 0; k < 3; ++k) {
+            ctx->gid[k] = (int32_t *)(b + L.gid[k]);
+            ctx->gvb[k] = (int32_t *)(b + L.gvb[k]);
+        }
+        ctx->gW = (int64_t *)(b + L.gW);
+        ctx->gsum = (unsigned long long *)(b + L.gsum);
+        ctx->gst = (int32_t *)(b + L.gst);
+        ctx->giter = (int32_t *)(b + L.giter);
+        ctx->gcomm = (int32_t *)(b + L.gcomm);
+        ctx->gsig = (unsigned long long *)(b + L.gsig);
+        ctx->gs2 = (unsigned long long *)(b + L.gs2);
+        // graph offsets: 0 = first <= ... <= last = n
+        std::vector<int32_t> go((size_t)G + 1);
+        if (hipMemcpy(go.data(), graph_offsets, sizeof(int32_t) * go.size(), hipMemcpyDefault) !=
+            hipSuccess) {
+            g_last_hip_error = "reading the graph offsets failed";
+            return fail(LOUVAIN_EHIP);
+        }
+        bool ok = go[0] == 0 && go[G] == n;
+        for (int g = 0; g < G && ok; ++g) ok = go[g] <= go[g + 1];
+        if (!ok) return fail(LOUVAIN_EINVAL);
+        if (hipMemcpyAsync(ctx->gvb[0], go.data(), sizeof(int32_t) * go.size(),
+                           hipMemcpyHostToDevice, ctx->s) != hipSuccess ||
+            hipStreamSynchronize(ctx->s) != hipSuccess) {
+            g_last_hip_error = "copying the graph offsets failed";
+            return fail(LOUVAIN_EHIP);
+        }
+        launch_batch_gid(n, ctx->gvb[0], G, ctx->gid[0], ctx->s);
+        launch_fill_bytes_zero(ctx->gW, 8 * (int64_t)G, ctx->s);
+        launch_batch_check(n, offsets, targets, weights, ctx->gid[0], ctx->gvb[0], ctx->gW,
+                           &ctx->sc->err, ctx->s);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(ctx->hsc, ctx->sc, offsetof(DevScalars, spread), hipMemcpyDeviceToHost,
+                           ctx->s) != hipSuccess ||
+            hipStreamSynchronize(ctx->s) != hipSuccess) {
+            g_last_hip_error = "batch validation failed";
+            return fail(LOUVAIN_EHIP);
+        }
+        if (ctx->hsc->err) return fail(LOUVAIN_EINVAL);
+    }
     launch_iota(ctx->top, n, ctx->s);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->s) != hipSuccess) {
         g_last_hip_error = "workspace initialisation failed";
         return fail(LOUVAIN_EHIP);
     }
     reset_state(ctx);
+    if (G > 0) {
+        launch_batch_reset(batch_args(ctx), ctx->gcomm, ctx->s);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->s) != hipSuccess) {
+            g_last_hip_error = "workspace initialisation failed";
+            return fail(LOUVAIN_EHIP);
+        }
+    }
     *out = ctx;
+    return LOUVAIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int louvain_init(louvain_ctx **out, int32_t n, int64_t nnz, const int32_t *offsets,
+                 const int32_t *targets, const int32_t *weights, void *workspace,
+                 size_t workspace_bytes, const louvain_params *p, void *stream)
+{
+    return init_ctx(out, 0, nullptr, n, nnz, offsets, targets, weights, workspace, workspace_bytes,
+                    p, stream);
+}
+
+int louvain_batch_workspace_size(int32_t graphs, int32_t n, int64_t nnz, int64_t total_weight,
+                                 const louvain_params *p, size_t *bytes)
+{
+    if (!bytes || graphs < 1 || n < 0 || nnz < 0) return LOUVAIN_EINVAL;
+    if (nnz > INT32_MAX) return LOUVAIN_EOVERFLOW;
+    if (p) {
+        const int r = check_params(p);
+        if (r) return r;
+    }
+    const int sb = (total_weight >= 0 && total_weight < ((int64_t)1 << 31)) ? 4 : 8;
+    *bytes = make_layout(n, nnz, sb, graphs).total;
+    return LOUVAIN_OK;
+}
+
+int louvain_init_batch(louvain_ctx **out, int32_t graphs, const int32_t *graph_offsets, int32_t n,
+                       int64_t nnz, const int32_t *offsets, const int32_t *targets,
+                       const int32_t *weights, void *workspace, size_t workspace_bytes,
+                       const louvain_params *p, void *stream)
+{
+    if (graphs < 1) return LOUVAIN_EINVAL;
+    return init_ctx(out, graphs, graph_offsets, n, nnz, offsets, targets, weights, workspace,
+                    workspace_bytes, p, stream);
+}
+
+int louvain_batch_results(louvain_ctx *ctx, double *modularity, int32_t *communities)
+{
+    if (!ctx || ctx->G <= 0) return LOUVAIN_EINVAL;
+    if (ctx->state != S_DONE) return LOUVAIN_ESTATE;
+    if (modularity)
+        for (int g = 0; g < ctx->G; ++g) modularity[g] = ctx->gq[g];
+    if (communities) {
+        CK(hipMemcpyAsync(communities, ctx->gcomm, sizeof(int32_t) * (size_t)ctx->G,
+                          hipMemcpyDeviceToHost, ctx->s));
+        TRY(sync_stream(ctx));
+    }
     return LOUVAIN_OK;
 }
 
@@ -1020,6 +1208,10 @@ int louvain_reset(louvain_ctx *ctx)
     reset_state(ctx);
     launch_iota(ctx->top, ctx->n, ctx->s);
     CKL();
+    if (ctx->G > 0) {
+        launch_batch_reset(batch_args(ctx), ctx->gcomm, ctx->s);
+        CKL();
+    }
     TRY(sync_stream(ctx));
     return LOUVAIN_OK;
 }

@@ -98,3 +98,22 @@ def test_product_path_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "louvain_oracle" not in text, f
+
+
+def test_batch_workspace_size_checks(lib):
+    import paper_2312_04876_amd as P
+    out = ctypes.c_size_t()
+    assert lib.louvain_batch_workspace_size(0, 10, 20, 20, None, ctypes.byref(out)) == \
+        P.binding.EINVAL
+    assert lib.louvain_batch_workspace_size(3, 10, 20, 20, None, ctypes.byref(out)) == P.binding.OK
+    batch = out.value
+    assert lib.louvain_workspace_size(10, 20, 20, None, ctypes.byref(out)) == P.binding.OK
+    assert batch > out.value
+
+
+def test_batch_init_rejects_bad_arguments_before_any_kernel(lib):
+    import paper_2312_04876_amd as P
+    ctx = ctypes.c_void_p()
+    assert lib.louvain_init_batch(ctypes.byref(ctx), 0, None, 0, 0, None, None, None, None, 0,
+                                  None, None) == P.binding.EINVAL
+    assert lib.louvain_batch_results(None, None, None) == P.binding.EINVAL

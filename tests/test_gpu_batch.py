@@ -1,0 +1,131 @@
+"""GPU batches: several independent graphs run as one union through the C ABI.
+
+Deterministic mode: every graph's membership and modularity equal those of the
+same graph run alone (which the parity suite pins to the oracle), bit for bit.
+Fast mode: every graph gets a valid partition whose reported Q equals the
+oracle's Q of that membership, within the fast-mode tolerance of the oracle's
+sequential Q.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from gpu_util import is_valid_partition, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2312_04876_amd as P
+    P.load_library()
+
+
+def _og(csr):
+    return oracle.as_graph(csr.offsets, csr.targets, csr.weights)
+
+
+def mixed_graphs():
+    """Uneven graphs, including an empty one, an edgeless one and ones that stop
+    after different numbers of passes."""
+    return [graphgen.sbm(300, 6, 0.2, 0.004, seed=11, name="sbm300"),
+            graphgen.from_edges(0, [], name="empty"),
+            graphgen.rmat(10, 8, seed=12, name="rmat10-8"),
+            graphgen.from_edges(5, [], name="isolated5"),
+            graphgen.cliques(4, 5, [(0, 5), (10, 15)], name="cliques"),
+            graphgen.from_edges(2, [(0, 1)], [3], name="edge"),
+            graphgen.sbm(2000, 20, 0.05, 0.001, seed=13, name="sbm2000"),
+            graphgen.rmat(12, 8, seed=14, name="rmat12-8"),
+            graphgen.rmat(14, 16, seed=15, name="rmat14-16")]
+
+
+def run_batch(graphs, **params):
+    import paper_2312_04876_amd as P
+    u, go = graphgen.union(graphs)
+    print("batch:", len(graphs), "graphs", u.n, "vertices", u.nnz, "entries", params, flush=True)
+    ctx = P.Louvain(*to_device(u), graph_offsets=go, **params)
+    try:
+        memb, q, st = ctx.run()
+        qs, comms = ctx.batch_results()
+        parts = ctx.split_membership(memb)
+    finally:
+        ctx.close()
+    return parts, qs, comms
+
+
+def alone(csr, **params):
+    import paper_2312_04876_amd as P
+    memb, q, _ = P.louvain(*to_device(csr), **params)
+    return memb.cpu().numpy()[:csr.n], q
+
+
+@pytest.mark.parametrize("round_bits", [1, 0, 2])
+def test_batch_det_equals_each_graph_alone(round_bits):
+    graphs = mixed_graphs()
+    parts, qs, comms = run_batch(graphs, mode="deterministic", round_bits=round_bits)
+    for g, csr in enumerate(graphs):
+        m1, q1 = alone(csr, mode="deterministic", round_bits=round_bits)
+        assert np.array_equal(parts[g], m1), csr.name
+        assert qs[g] == q1, csr.name
+        assert comms[g] == (len(np.unique(m1)) if csr.n else 0), csr.name
+        assert qs[g] == oracle.modularity(_og(csr), parts[g]), csr.name
+
+
+def test_batch_det_limits_and_reset():
+    import paper_2312_04876_amd as P
+    graphs = mixed_graphs()
+    for kw in ({"max_passes": 1}, {"max_iterations": 2}, {"prune": False}):
+        parts, qs, _ = run_batch(graphs, mode="deterministic", **kw)
+        for g, csr in enumerate(graphs):
+            m1, q1 = alone(csr, mode="deterministic", **kw)
+            assert np.array_equal(parts[g], m1) and qs[g] == q1, (csr.name, kw)
+    u, go = graphgen.union(graphs)
+    ctx = P.Louvain(*to_device(u), graph_offsets=go, mode="deterministic")
+    m1, _, _ = ctx.run()
+    m1 = m1.cpu().numpy().copy()
+    ctx.reset()
+    m2, _, _ = ctx.run()
+    assert np.array_equal(m1, m2.cpu().numpy())
+    ctx.close()
+
+
+def test_batch_of_sbm_recipe_det():
+    u, go, specs = graphgen.batch_sbm(24, seed=4, n_max=3000)
+    graphs = [graphgen.CSR(int(go[g + 1] - go[g]),
+                           u.offsets[go[g]:go[g + 1] + 1] - u.offsets[go[g]],
+                           u.targets[u.offsets[go[g]]:u.offsets[go[g + 1]]] - go[g],
+                           u.weights[u.offsets[go[g]]:u.offsets[go[g + 1]]],
+                           "g%d" % g) for g in range(len(specs))]
+    parts, qs, _ = run_batch(graphs, mode="deterministic")
+    for g, csr in enumerate(graphs):
+        m1, q1 = alone(csr, mode="deterministic")
+        assert np.array_equal(parts[g], m1) and qs[g] == q1, csr.name
+
+
+def test_batch_fast_quality():
+    graphs = [graphgen.sbm(3000, 30, 0.05, 0.0005, seed=21, name="sbm3000"),
+              graphgen.rmat(14, 16, seed=22, name="rmat14-16"),
+              graphgen.sbm(10000, 100, 0.05, 0.0005, seed=1, name="sbm10k"),
+              graphgen.rmat(16, 16, seed=2, name="rmat16-16")]
+    parts, qs, _ = run_batch(graphs, mode="fast")
+    for g, csr in enumerate(graphs):
+        og = _og(csr)
+        assert is_valid_partition(parts[g]), csr.name
+        assert qs[g] == oracle.modularity(og, parts[g]), csr.name
+        _, q_seq, _ = oracle.louvain(og, oracle.Params(mode="seq"))
+        if csr.name.startswith("rmat"):
+            assert abs(qs[g] - q_seq) <= 0.01, (csr.name, qs[g], q_seq)
+        else:
+            assert qs[g] >= q_seq - 0.01, (csr.name, qs[g], q_seq)
+
+
+def test_batch_rejects_an_edge_between_graphs():
+    import paper_2312_04876_amd as P
+    csr = graphgen.from_edges(4, [(0, 1), (1, 2), (2, 3)], name="path")
+    with pytest.raises(P.LouvainError):
+        P.Louvain(*to_device(csr), graph_offsets=np.array([0, 2, 4], dtype=np.int32))
+    with pytest.raises(P.LouvainError):
+        P.Louvain(*to_device(csr), graph_offsets=np.array([0, 3, 2, 4], dtype=np.int32))
