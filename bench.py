@@ -53,6 +53,11 @@ def parse():
                     help="summarise four rocprofv3 --pmc output directories (FETCH_SIZE and "
                          "WRITE_SIZE of one bench step, then of the copy probe) into --pmc-out")
     ap.add_argument("--pmc-out", default=os.path.join(ROOT, "profiles", "rmat22_fast_pmc.json"))
+    ap.add_argument("--batch", type=int, default=0, metavar="G",
+                    help="only run the batched workload: G planted-partition SBMs of uneven size "
+                         "(n log-uniform 200..50,000, mean degree 8..40, p_out/p_in = 0.02) as one "
+                         "union run, against the same graphs run one by one")
+    ap.add_argument("--batch-nmax", type=int, default=50_000)
     return ap.parse_args()
 
 
@@ -187,8 +192,84 @@ def cpu_baseline(name):
             "seconds": round(dt, 3)}
 
 
+def batch_main(args):
+    """Batched workload: one union run of G graphs vs G per-graph runs (inputs resident)."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2312_04876_amd as P
+
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    u, go, specs = graphgen.batch_sbm(args.batch, seed=4, threads=threads, n_max=args.batch_nmax)
+    print("generated %d graphs: n=%d nnz=%d in %.1fs" % (args.batch, u.n, u.nnz,
+                                                         time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    opts = dict(mode=args.mode, round_bits=args.round_bits)
+    off = torch.from_numpy(u.offsets32()).to(dev)
+    tgt = torch.from_numpy(u.targets).to(dev)
+    w = torch.from_numpy(u.weights).to(dev)
+    memb = torch.empty(max(u.n, 1), dtype=torch.int32, device=dev)
+    ctx = P.Louvain(off, tgt, w, graph_offsets=go, **opts)
+    run_steps(ctx, memb, args.warmup)
+    sec_b, (m, _q, st) = run_steps(ctx, memb, args.steps)
+    q_b, comm_b = ctx.batch_results()
+    ctx.close()
+    print("batched: %.1f ms per batch, %.3g edges/s, passes %d" %
+          (sec_b * 1e3, u.nnz / sec_b, st["passes"]), file=sys.stderr, flush=True)
+    # the same graphs one by one (each resident with its own context)
+    ctxs = []
+    for g in range(args.batch):
+        a, b = int(go[g]), int(go[g + 1])
+        e0, e1 = int(u.offsets[a]), int(u.offsets[b])
+        o = torch.from_numpy((u.offsets[a:b + 1] - e0).astype(np.int32)).to(dev)
+        t = torch.from_numpy(u.targets[e0:e1] - np.int32(a)).to(dev)
+        ww = torch.from_numpy(u.weights[e0:e1]).to(dev)
+        ctxs.append((P.Louvain(o, t, ww, **opts), torch.empty(max(b - a, 1), dtype=torch.int32,
+                                                               device=dev)))
+    q_s = [0.0] * args.batch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, (c, mm) in enumerate(ctxs):
+        c.reset()
+        _, q_s[g], _ = c.run(mm)
+    torch.cuda.synchronize()
+    sec_s = time.perf_counter() - t0
+    for c, _ in ctxs:
+        c.close()
+    print("one by one: %.1f ms, %.3g edges/s" % (sec_s * 1e3, u.nnz / sec_s), file=sys.stderr,
+          flush=True)
+    dq = [abs(a - b) for a, b in zip(q_b, q_s)]
+    line = {
+        "metric": "edges/s of a batch of graphs (one union run) vs the same graphs run one by one",
+        "value": u.nnz / sec_b, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec_b * 1e3, "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "int32/int64",
+        "data": "synthetic: %d planted-partition SBMs, n log-uniform 200..%d, mean degree 8..40, "
+                "4..200 blocks, p_out/p_in 0.02, unit weights, seed 4" % (args.batch,
+                                                                            args.batch_nmax),
+        "config": {"workload": "batch%d" % args.batch, "graphs": args.batch, "n": u.n,
+                   "nnz": u.nnz, "mode": args.mode, "round_bits": args.round_bits},
+        "one_by_one": {"value": u.nnz / sec_s, "ms": sec_s * 1e3},
+        "speedup": sec_s / sec_b,
+        "max_abs_q_difference": max(dq) if dq else 0.0,
+        "identical_q": sum(1 for d in dq if d == 0.0),
+        "mean_q": float(np.mean(q_b)) if q_b else 0.0,
+        "passes": st["passes"],
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
+    if args.batch:
+        if args.gpus != 1:
+            print("bench.py measures one GPU; use --gpus 1", file=sys.stderr)
+            sys.exit(2)
+        batch_main(args)
+        return
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
