@@ -58,6 +58,13 @@ def parse():
                          "(n log-uniform 200..50,000, mean degree 8..40, p_out/p_in = 0.02) as one "
                          "union run, against the same graphs run one by one")
     ap.add_argument("--batch-nmax", type=int, default=50_000)
+    ap.add_argument("--serve", type=float, nargs="*", metavar="RATE",
+                    help="only run the serving workload: Poisson arrivals at each RATE jobs/s "
+                         "drawn from a pool of SBM and R-MAT graphs")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-pool", type=int, default=1024)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=float, default=160.0)
     return ap.parse_args()
 
 
@@ -262,8 +269,92 @@ def batch_main(args):
     print(json.dumps(line))
 
 
+def serve_main(args):
+    """Serving workload: Poisson arrivals from a resident pool; p50/p99 latency and edges/s."""
+    import random
+    import threading
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    from paper_2312_04876_amd.serve import GpuExecutor, Job, Server, latency_stats
+
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    pool = {k: g for k, g in enumerate(graphgen.serving_pool(args.serve_pool, seed=5,
+                                                             threads=threads))}
+    nnz = np.array([g.nnz for g in pool.values()])
+    print("pool of %d graphs: median %d entries, mean %d, max %d, generated in %.1fs" %
+          (len(pool), int(np.median(nnz)), int(nnz.mean()), int(nnz.max()),
+           time.perf_counter() - t0), file=sys.stderr, flush=True)
+    ex = GpuExecutor(pool, slots=args.serve_slots, mode=args.mode, round_bits=args.round_bits)
+    # warm-up: one small batch on every slot
+    warm = Server(ex, memory_budget=int(args.serve_budget_gib * (1 << 30)), slots=args.serve_slots)
+    for k in range(2 * args.serve_slots):
+        warm.submit(Job(key=k, nnz=pool[k].nnz, n=pool[k].n))
+    warm.close()
+    results = []
+    for rate in args.serve:
+        rng = random.Random(5)
+        srv = Server(ex, memory_budget=int(args.serve_budget_gib * (1 << 30)),
+                     slots=args.serve_slots)
+        jobs = []
+        start = time.perf_counter()
+
+        def feed():
+            t = start
+            while True:
+                t += rng.expovariate(rate)
+                if t - start > args.serve_seconds:
+                    return
+                d = t - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                k = rng.randrange(len(pool))
+                jobs.append(srv.submit(Job(key=k, nnz=pool[k].nnz, n=pool[k].n)))
+
+        th = threading.Thread(target=feed)
+        th.start()
+        th.join()
+        srv.drain()
+        end = time.perf_counter()
+        srv.close()
+        done = [j for j in jobs if j.error is None]
+        st = latency_stats(jobs)
+        ent = sum(j.nnz for j in done)
+        res = {"rate_jobs_per_s": rate, "jobs": len(jobs), "completed": len(done),
+               "failed": len(jobs) - len(done), "batches": srv.batches,
+               "p50_ms": st.get("p50_ms"), "p99_ms": st.get("p99_ms"), "max_ms": st.get("max_ms"),
+               "edges_per_s": ent / (end - start), "offered_edges_per_s":
+                   sum(j.nnz for j in jobs) / args.serve_seconds,
+               "wall_s": end - start, "peak_memory_gib": srv.peak_memory / (1 << 30)}
+        results.append(res)
+        print("rate %.0f/s: %d jobs, %d batches, p50 %.1f ms p99 %.1f ms, %.3g edges/s" %
+              (rate, len(jobs), srv.batches, res["p50_ms"] or 0, res["p99_ms"] or 0,
+               res["edges_per_s"]), file=sys.stderr, flush=True)
+    best = results[-1] if results else {}
+    line = {"metric": "p50/p99 job latency and edges/s of the continuous-batching server",
+            "value": best.get("edges_per_s"), "unit": "edges/s", "n_gpus": 1,
+            "steps": len(results), "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "strong", "vs_baseline": None, "dtype": "int32/int64",
+            "data": "synthetic: pool of %d graphs, half SBM half R-MAT, entries log-normal "
+                    "(median 2e5, sigma 1.5, cap 5e7), Poisson arrivals, seed 5" % len(pool),
+            "config": {"workload": "serve", "mode": args.mode, "slots": args.serve_slots,
+                       "seconds": args.serve_seconds,
+                       "memory_budget_gib": args.serve_budget_gib},
+            "rates": results}
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
+    if args.serve:
+        if args.gpus != 1:
+            print("bench.py measures one GPU; use --gpus 1", file=sys.stderr)
+            sys.exit(2)
+        serve_main(args)
+        return
     if args.batch:
         if args.gpus != 1:
             print("bench.py measures one GPU; use --gpus 1", file=sys.stderr)

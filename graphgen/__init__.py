@@ -29,7 +29,7 @@ import os
 import re
 import subprocess
 from dataclasses import dataclass
-from typing import Iterable, Optional, Sequence, Tuple
+from typing import Iterable, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -229,6 +229,55 @@ def batch_sbm(count: int, seed: int = 4, threads: int = 0, **kw) -> Tuple[CSR, n
               for sp in specs]
     u, go = union(graphs, name="batch%d" % count)
     return u, go, specs
+
+
+def serving_pool_specs(count: int, seed: int = 5, median: float = 2e5, sigma: float = 1.5,
+                       cap: float = 5e7):
+    """Parameters of a pool of `count` graphs for a serving workload: entry count
+    log-normal (median, sigma) capped at `cap`; half SBMs (mean degree uniform in
+    [8, 40], n = entries / degree, 4..200 blocks, p_out = 0.02 p_in), half R-MATs
+    (scale ceil(log2(entries / 32)), entries / 2 draws).  Graph g draws from
+    SplitMix64 under key (seed << 32) | g."""
+    specs = []
+    for g in range(count):
+        key = ((int(seed) << 32) | g) & ((1 << 64) - 1)
+        u = [splitmix_draw(key, c) / 2.0 ** 64 for c in range(5)]
+        z = math.sqrt(-2.0 * math.log(max(u[0], 1e-300))) * math.cos(2.0 * math.pi * u[1])
+        e = min(math.exp(math.log(median) + sigma * z), cap)
+        e = max(e, 64.0)
+        if u[2] < 0.5:
+            scale = max(1, int(math.ceil(math.log2(e / 32.0))))
+            ef = max(1, int(round(e / 2.0 / (1 << scale))))
+            specs.append({"kind": "rmat", "scale": scale, "edge_factor": ef,
+                          "seed": (key + 1) & ((1 << 64) - 1)})
+        else:
+            dbar = 8.0 + 32.0 * u[3]
+            n = max(16, int(round(e / dbar)))
+            k = 4 + int(u[4] * 197)
+
+            def p_in_of(kk):
+                sz = n / kk
+                return dbar / ((sz - 1.0) + 0.02 * (n - sz))
+            while k > 1 and (n / k < 2 or p_in_of(k) > 1.0):
+                k -= 1
+            k = max(k, 1)
+            p_in = min(1.0, p_in_of(k))
+            specs.append({"kind": "sbm", "n": n, "k": k, "p_in": p_in, "p_out": 0.02 * p_in,
+                          "seed": (key + 1) & ((1 << 64) - 1)})
+    return specs
+
+
+def serving_pool(count: int, seed: int = 5, threads: int = 0, **kw) -> List[CSR]:
+    """The graphs of serving_pool_specs."""
+    out = []
+    for g, sp in enumerate(serving_pool_specs(count, seed, **kw)):
+        if sp["kind"] == "rmat":
+            out.append(rmat(sp["scale"], sp["edge_factor"], seed=sp["seed"], threads=threads,
+                            name="pool%d" % g))
+        else:
+            out.append(sbm(sp["n"], sp["k"], sp["p_in"], sp["p_out"], seed=sp["seed"],
+                           threads=threads, name="pool%d" % g))
+    return out
 
 
 _RMAT = re.compile(r"^rmat(\d+)-(\d+)$")

@@ -1006,8 +1006,9 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
         ctx->gs2 = (unsigned long long *)(b + L.gs2);
         // graph offsets: 0 = first <= ... <= last = n
         std::vector<int32_t> go((size_t)G + 1);
-        if (hipMemcpy(go.data(), graph_offsets, sizeof(int32_t) * go.size(), hipMemcpyDefault) !=
-            hipSuccess) {
+        if (hipMemcpyAsync(go.data(), graph_offsets, sizeof(int32_t) * go.size(), hipMemcpyDefault,
+                           ctx->s) != hipSuccess ||
+            hipStreamSynchronize(ctx->s) != hipSuccess) {
             g_last_hip_error = "reading the graph offsets failed";
             return fail(LOUVAIN_EHIP);
         }
