@@ -72,6 +72,10 @@ __host__ __device__ inline int hub_parts(int64_t d)
 // member entries, folded in a table of twice as many slots.
 constexpr int AGG_PLOG2 = 12;
 constexpr int AGG_PSLICE = 1 << AGG_PLOG2;
+// Member entries per hash partition of a hub community: windows fold repeated
+// neighbours first, so partitions are cut for several times more entries than
+// an LDS partition table holds pairs.
+constexpr int AGG_PART_ENTRIES = 4096;
 // Rows per workgroup of the binning and compaction kernels.
 constexpr int BIN_CHUNK = 4096;
 // Vertices per workgroup (and LDS table slots / 2) of the community counting kernels.

@@ -270,14 +270,16 @@ __global__ __launch_bounds__(256) void k_bin_fill(int32_t n, const int32_t *off,
 
 __global__ void k_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he,
                                  const int32_t *off, const int32_t *deg, int stbytes,
-                                 int64_t *ent, int32_t *slices, int32_t *parts, int slice)
+                                 int64_t *ent, int32_t *slices, int32_t *parts, int slice,
+                                 int per_part)
 {
     for (int64_t p = hb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < he;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = len_of(off, deg, binorder[p]);
         ent[p - hb] = d;
         slices[p - hb] = (int32_t)((d + slice - 1) / slice);
-        parts[p - hb] = stbytes == 4 ? hub_parts<int32_t>(d) : hub_parts<int64_t>(d);
+        const int64_t q = (d + per_part - 1) / per_part;
+        parts[p - hb] = (int32_t)(q < 1 ? 1 : (q > HUB_MAXP ? HUB_MAXP : q));
     }
 }
 
@@ -879,11 +881,12 @@ void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, int32_t 
 
 void launch_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
                            const int32_t *deg, int stbytes, int64_t *ent, int32_t *slices,
-                           int32_t *parts, hipStream_t s, int slice)
+                           int32_t *parts, hipStream_t s, int slice, int per_part)
 {
+    if (per_part <= 0) per_part = stbytes == 4 ? hub_part_pairs<int32_t>() : hub_part_pairs<int64_t>();
     if (he > hb)
         k_hub_move_sizes<<<grid_for(he - hb, 256), 256, 0, s>>>(binorder, hb, he, off, deg, stbytes,
-                                                                ent, slices, parts, slice);
+                                                                ent, slices, parts, slice, per_part);
 }
 
 void launch_member_degrees(int32_t n, const int32_t *members, const int32_t *off,

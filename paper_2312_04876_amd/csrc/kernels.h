@@ -48,10 +48,12 @@ void launch_bin_fill(int32_t n, const int32_t *off, const int32_t *deg, int32_t 
                      const int32_t *boff, int32_t *binorder, hipStream_t s);
 // Hub bin rows binorder[hb .. he) (row lengths from off/deg, or from deg alone
 // when off is null): length (ent), sorting slices of `slice` entries (slices)
-// and hash partitions (parts, for table values of stbytes bytes).
+// and hash partitions of about per_part entries each (parts; 0 = the LDS
+// partition size for table values of stbytes bytes), at most HUB_MAXP.
 void launch_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he, const int32_t *off,
                            const int32_t *deg, int stbytes, int64_t *ent, int32_t *slices,
-                           int32_t *parts, hipStream_t s, int slice = HUB_PSLICE);
+                           int32_t *parts, hipStream_t s, int slice = HUB_PSLICE,
+                           int per_part = 0);
 
 // mdeg[m] = row length of members[m].
 void launch_member_degrees(int32_t n, const int32_t *members, const int32_t *off,

@@ -634,7 +634,7 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
                                                 s);
         launch_hub_move_sizes(ctx->cbinorder, cb.start[NBINS - 1], cb.start[NBINS], nullptr,
                               ctx->ctot, (int)sizeof(ST), ctx->hsz, ctx->cursor, ctx->ccount, s,
-                              AGG_PSLICE);
+                              AGG_PSLICE, AGG_PART_ENTRIES);
         launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->slA, hubs, ctx->scratch,
                                                 &ctx->sc->hub_slices, s);
         launch_exclusive_scan<int32_t, int32_t>(ctx->ccount, ctx->slB, hubs, ctx->scratch,
