@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--serve-pool", type=int, default=1024)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=float, default=160.0)
+    ap.add_argument("--dynamic", type=float, nargs="*", metavar="FRAC",
+                    help="only run the dynamic workload: after an edge batch that deletes and "
+                         "inserts FRAC of the edges, a cold run against a run warm-started from "
+                         "the membership before the batch")
     return ap.parse_args()
 
 
@@ -347,8 +351,81 @@ def serve_main(args):
     print(json.dumps(line))
 
 
+def dynamic_main(args):
+    """Dynamic workload: cold vs warm-started runs after edge batches of each size."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2312_04876_amd as P
+
+    threads = min(16, os.cpu_count() or 1)
+    csr = graphgen.workload(args.workload, threads=threads)
+    dev = torch.device("cuda:0")
+
+    def upload(c):
+        return (torch.from_numpy(c.offsets32()).to(dev), torch.from_numpy(c.targets).to(dev),
+                torch.from_numpy(c.weights).to(dev))
+    opts = dict(mode=args.mode, round_bits=args.round_bits)
+    base = P.Louvain(*upload(csr), **opts)
+    m0, q0, _ = base.run()
+    m0 = m0.clone()
+    base.close()
+    rows = []
+    for frac in args.dynamic:
+        t0 = time.perf_counter()
+        g2 = graphgen.perturb(csr, frac, seed=9)
+        print("edge batch %.4g: %d -> %d entries in %.1fs" % (frac, csr.nnz, g2.nnz,
+                                                              time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+        ctx = P.Louvain(*upload(g2), **opts)
+        memb = torch.empty(g2.n, dtype=torch.int32, device=dev)
+
+        def timed(warm):
+            res = None
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.reset()
+                if warm:
+                    ctx.set_membership(m0)
+                res = ctx.run(memb)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / args.steps, res
+        for _ in range(args.warmup):
+            timed(False)
+            timed(True)
+        cold_s, (_, cold_q, cold_st) = timed(False)
+        warm_s, (_, warm_q, warm_st) = timed(True)
+        ctx.close()
+        row = {"fraction": frac, "entries": g2.nnz, "cold_ms": cold_s * 1e3, "cold_q": cold_q,
+               "cold_iterations": cold_st["iterations"], "warm_ms": warm_s * 1e3,
+               "warm_q": warm_q, "warm_iterations": warm_st["iterations"],
+               "speedup": cold_s / warm_s}
+        rows.append(row)
+        print("  cold %.2f ms Q=%.5f its %s | warm %.2f ms Q=%.5f its %s" %
+              (cold_s * 1e3, cold_q, cold_st["iterations"], warm_s * 1e3, warm_q,
+               warm_st["iterations"]), file=sys.stderr, flush=True)
+    line = {"metric": "edges/s of a warm-started re-run after an edge batch (vs a cold run)",
+            "value": rows[-1]["entries"] / (rows[-1]["warm_ms"] * 1e-3) if rows else None,
+            "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": rows[-1]["warm_ms"] if rows else None, "higher_is_better": True,
+            "scaling": "strong", "vs_baseline": None, "dtype": "int32/int64",
+            "data": "synthetic: %s, then edge batches deleting and inserting a share of its "
+                    "edges (seed 9)" % WORKLOADS.get(args.workload, args.workload),
+            "config": {"workload": args.workload + "-dynamic", "mode": args.mode,
+                       "base_q": q0}, "batches": rows}
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
+    if args.dynamic:
+        if args.gpus != 1:
+            print("bench.py measures one GPU; use --gpus 1", file=sys.stderr)
+            sys.exit(2)
+        dynamic_main(args)
+        return
     if args.serve:
         if args.gpus != 1:
             print("bench.py measures one GPU; use --gpus 1", file=sys.stderr)

@@ -231,6 +231,48 @@ def batch_sbm(count: int, seed: int = 4, threads: int = 0, **kw) -> Tuple[CSR, n
     return u, go, specs
 
 
+def perturb(csr: CSR, frac: float, seed: int = 9, name: str = "") -> CSR:
+    """An edge batch applied to `csr`: a `frac` share of its undirected non-loop edges
+    deleted and as many new unit-weight edges between random distinct vertices
+    inserted (merged into existing pairs by summing), from numpy's seeded generator."""
+    n = csr.n
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(csr.offsets))
+    tgt = csr.targets[:csr.nnz].astype(np.int64)
+    w = csr.weights[:csr.nnz].astype(np.int64)
+    up = src < tgt
+    loop = src == tgt
+    u, v, ww = src[up], tgt[up], w[up]
+    rng = np.random.default_rng(seed)
+    k = int(frac * len(u))
+    keep = np.ones(len(u), dtype=bool)
+    if k:
+        keep[rng.choice(len(u), size=k, replace=False)] = False
+    a = rng.integers(0, n, size=k, dtype=np.int64)
+    b = rng.integers(0, n, size=k, dtype=np.int64)
+    ok = a != b
+    a, b = np.minimum(a[ok], b[ok]), np.maximum(a[ok], b[ok])
+    U = np.concatenate([u[keep], a, v[keep], b, src[loop]])
+    V = np.concatenate([v[keep], b, u[keep], a, tgt[loop]])
+    Wt = np.concatenate([ww[keep], np.ones(len(a), np.int64), ww[keep], np.ones(len(a), np.int64),
+                         w[loop]])
+    key = U * n + V
+    order = np.argsort(key, kind="stable")
+    key, Wt = key[order], Wt[order]
+    first = np.ones(len(key), dtype=bool)
+    first[1:] = key[1:] != key[:-1]
+    idx = np.flatnonzero(first)
+    wsum = np.add.reduceat(Wt, idx) if len(idx) else Wt[:0]
+    if len(wsum) and wsum.max() >= 2 ** 31:
+        raise ValueError("merged weight exceeds int32")
+    ukey = key[idx]
+    rows = ukey // n
+    off = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(off, rows + 1, 1)
+    off = np.cumsum(off)
+    return CSR(n, off, (ukey % n).astype(np.int32), wsum.astype(np.int32),
+               name or "%s+%g" % (csr.name, frac))
+
+
 def serving_pool_specs(count: int, seed: int = 5, median: float = 2e5, sigma: float = 1.5,
                        cap: float = 5e7):
     """Parameters of a pool of `count` graphs for a serving workload: entry count

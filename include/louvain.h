@@ -225,6 +225,19 @@ int louvain_kernel_stats(louvain_ctx *ctx, louvain_kernel_stat *out, int32_t max
                          int32_t *count);
 
 /*
+ * Warm start (the dynamic re-run the Conclusion names as future work: after edge
+ * updates, start from the previous membership): the first pass's local
+ * moving starts from the partition `labels` (device int32[n], each in [0, n),
+ * and in a batch inside its own graph's range) instead of singletons, with
+ * the community weights and sizes of that partition; the rest of the method
+ * is unchanged.  The caller keeps `labels` valid until the first pass has
+ * moved; NULL clears it, and louvain_reset forgets it.  Only before the first
+ * louvain_move of a run.
+ * Errors: EINVAL (NULL ctx, a label out of range), ESTATE (a pass has begun), EHIP.
+ */
+int louvain_set_membership(louvain_ctx *ctx, const int32_t *labels);
+
+/*
  * Batches: several independent graphs run through one launch sequence as
  * the union of their CSRs (graph g owns the vertices [graph_offsets[g],
  * graph_offsets[g+1]) and only edges among them).  Every graph keeps its

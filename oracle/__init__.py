@@ -84,6 +84,9 @@ def _load():
         lib.oracle_louvain.restype = i32
         lib.oracle_louvain.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, u64, i32, i32, vp,
                                        vp, vp, vp, vp, vp, vp, vp]
+        lib.oracle_louvain_from.restype = i32
+        lib.oracle_louvain_from.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, u64, i32, i32,
+                                            vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = lib
     return _lib
 
@@ -178,6 +181,21 @@ class MoveState:
         return MoveState(K=K, W=W, Sigma=K.copy(), C=np.arange(g.n, dtype=np.int32),
                          size=np.ones(g.n, dtype=np.int32), active=np.ones(g.n, dtype=np.uint8))
 
+    @staticmethod
+    def warm(g: Graph, labels) -> "MoveState":
+        """Start from the partition `labels` (each in [0, n)): Sigma_c and |c| of it."""
+        K, W = vertex_weights(g)
+        C = np.asarray(labels, dtype=np.int32).copy()
+        if C.shape != (g.n,) or (g.n and (C.min() < 0 or C.max() >= g.n)):
+            raise ValueError("labels must be n values in [0, n)")
+        Sigma = np.zeros(g.n, dtype=np.int64)
+        size = np.zeros(g.n, dtype=np.int32)
+        for i in range(g.n):
+            Sigma[C[i]] += int(K[i])
+            size[C[i]] += 1
+        return MoveState(K=K, W=W, Sigma=Sigma, C=C, size=size,
+                         active=np.ones(g.n, dtype=np.uint8))
+
 
 @dataclass
 class MoveTrace:
@@ -259,8 +277,9 @@ class Params:
     sample_bits: int = 1   # a synchronous iteration runs in 2**sample_bits rounds
 
 
-def louvain(g: Graph, params: Optional[Params] = None):
-    """Alg. 1 entirely in C. Returns (membership int32[n], Q, records dict)."""
+def louvain(g: Graph, params: Optional[Params] = None, initial=None):
+    """Alg. 1 entirely in C. Returns (membership int32[n], Q, records dict).
+    ``initial``: labels of a partition the first pass starts from (a warm start)."""
     p = params or Params()
     mp = max(p.max_passes, 1)
     memb = np.zeros(max(g.n, 1), dtype=np.int32)
@@ -268,11 +287,17 @@ def louvain(g: Graph, params: Optional[Params] = None):
     it = np.zeros(mp, dtype=np.int32)
     nv = np.zeros(mp, dtype=np.int32)
     nc = np.zeros(mp, dtype=np.int32)
-    passes = _load().oracle_louvain(_MODES[p.mode], p.max_passes, p.max_iterations,
-                                    1 if p.prune else 0, p.tolerance, p.tolerance_drop,
-                                    p.aggregation_tolerance, int(p.seed) & ((1 << 64) - 1),
-                                    int(p.sample_bits), g.n, _p(g.offsets), _p(g.targets),
-                                    _p(g.weights), _p(memb), ctypes.byref(q), _p(it), _p(nv), _p(nc))
+    init = None
+    if initial is not None:
+        init = np.ascontiguousarray(initial, dtype=np.int32)
+        if init.shape != (g.n,) or (g.n and (init.min() < 0 or init.max() >= g.n)):
+            raise ValueError("initial labels must be n values in [0, n)")
+    passes = _load().oracle_louvain_from(_MODES[p.mode], p.max_passes, p.max_iterations,
+                                         1 if p.prune else 0, p.tolerance, p.tolerance_drop,
+                                         p.aggregation_tolerance, int(p.seed) & ((1 << 64) - 1),
+                                         int(p.sample_bits), g.n, _p(g.offsets), _p(g.targets),
+                                         _p(g.weights), _p(init) if init is not None else None,
+                                         _p(memb), ctypes.byref(q), _p(it), _p(nv), _p(nc))
     if passes < 0:
         raise RuntimeError("oracle_louvain failed")
     rec = {"passes": int(passes), "iterations": it[:passes].tolist(),
@@ -291,8 +316,9 @@ class PassRecord:
     top: np.ndarray              # top-level membership C after the pass
 
 
-def louvain_trace(g: Graph, params: Optional[Params] = None):
-    """Alg. 1 driven step by step; returns (membership, Q, [PassRecord])."""
+def louvain_trace(g: Graph, params: Optional[Params] = None, initial=None):
+    """Alg. 1 driven step by step; returns (membership, Q, [PassRecord]).
+    ``initial``: labels of a partition the first pass starts from (a warm start)."""
     p = params or Params()
     top = np.arange(g.n, dtype=np.int32)
     level = g
@@ -301,7 +327,8 @@ def louvain_trace(g: Graph, params: Optional[Params] = None):
     recs: List[PassRecord] = []
     Cp = np.zeros(0, dtype=np.int32)
     for pi in range(p.max_passes):
-        st = MoveState.fresh(level)
+        st = MoveState.warm(level, initial) if (pi == 0 and initial is not None) \
+            else MoveState.fresh(level)
         tr = move(level, st, p.mode, tau, p.max_iterations, p.prune, p.seed, pi, p.sample_bits)
         Cp = st.C.copy()
         ncomm = int(len(np.unique(Cp))) if level.n else 0

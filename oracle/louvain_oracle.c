@@ -503,14 +503,19 @@ int64_t oracle_aggregate(int32_t n, const int64_t *off, const int32_t *tgt,
  * Returns the number of passes whose local-moving phase ran, or a negative
  * value on failure.
  */
-int32_t oracle_louvain(int32_t mode, int32_t max_passes, int32_t max_iter,
-                       int32_t prune, double tolerance, double tolerance_drop,
-                       double aggregation_tolerance, uint64_t seed,
-                       int32_t sample_bits, int32_t n,
-                       const int64_t *off, const int32_t *tgt,
-                       const int64_t *w, int32_t *membership, double *Q,
-                       int32_t *rec_iters, int32_t *rec_vertices,
-                       int32_t *rec_comms)
+/* Alg. 1, optionally warm-started: with `initial` non-NULL the first pass's
+ * local moving starts from those labels (each in [0, n)) instead of
+ * singletons, with Sigma and the community sizes of that partition; later
+ * passes start from singletons of their aggregated graph as usual. */
+int32_t oracle_louvain_from(int32_t mode, int32_t max_passes, int32_t max_iter,
+                            int32_t prune, double tolerance, double tolerance_drop,
+                            double aggregation_tolerance, uint64_t seed,
+                            int32_t sample_bits, int32_t n,
+                            const int64_t *off, const int32_t *tgt,
+                            const int64_t *w, const int32_t *initial,
+                            int32_t *membership, double *Q,
+                            int32_t *rec_iters, int32_t *rec_vertices,
+                            int32_t *rec_comms)
 {
     int64_t nnz = off[n];
     size_t m = (size_t)(n > 0 ? n : 1);
@@ -555,6 +560,17 @@ int32_t oracle_louvain(int32_t mode, int32_t max_passes, int32_t max_iter,
             size[i] = 1;
             active[i] = 1;
         }
+        if (p == 0 && initial) {
+            for (int32_t i = 0; i < ln; ++i) {
+                Sig[i] = 0;
+                size[i] = 0;
+            }
+            for (int32_t i = 0; i < ln; ++i) {
+                Cp[i] = initial[i];
+                Sig[initial[i]] += K[i];
+                size[initial[i]] += 1;
+            }
+        }
         int32_t l = oracle_move(mode, ln, loff, ltgt, lw, K, W, Sig, Cp, size,
                                 active, prune, tau, max_iter, seed, p,
                                 sample_bits, NULL, NULL, NULL, NULL);
@@ -591,4 +607,19 @@ int32_t oracle_louvain(int32_t mode, int32_t max_passes, int32_t max_iter,
     free(offA); free(tgtA); free(wA); free(offB); free(tgtB); free(wB);
     free(K); free(Sig); free(Cp); free(size); free(active);
     return rc == 0 ? passes : rc;
+}
+
+int32_t oracle_louvain(int32_t mode, int32_t max_passes, int32_t max_iter,
+                       int32_t prune, double tolerance, double tolerance_drop,
+                       double aggregation_tolerance, uint64_t seed,
+                       int32_t sample_bits, int32_t n,
+                       const int64_t *off, const int32_t *tgt,
+                       const int64_t *w, int32_t *membership, double *Q,
+                       int32_t *rec_iters, int32_t *rec_vertices,
+                       int32_t *rec_comms)
+{
+    return oracle_louvain_from(mode, max_passes, max_iter, prune, tolerance,
+                               tolerance_drop, aggregation_tolerance, seed,
+                               sample_bits, n, off, tgt, w, NULL, membership, Q,
+                               rec_iters, rec_vertices, rec_comms);
 }

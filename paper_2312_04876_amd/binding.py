@@ -28,6 +28,7 @@ EXPORTS = (
     "louvain_level_graph", "louvain_move_trace", "louvain_reset", "louvain_total_weight",
     "louvain_get_stats", "louvain_kernel_stats", "louvain_destroy", "louvain_strerror",
     "louvain_batch_workspace_size", "louvain_init_batch", "louvain_batch_results",
+    "louvain_set_membership",
 )
 
 
@@ -121,6 +122,8 @@ def load_library():
                                        P(CParams), vp]
     lib.louvain_batch_results.restype = ctypes.c_int
     lib.louvain_batch_results.argtypes = [vp, vp, vp]
+    lib.louvain_set_membership.restype = ctypes.c_int
+    lib.louvain_set_membership.argtypes = [vp, vp]
     lib.louvain_destroy.restype = None
     lib.louvain_destroy.argtypes = [vp]
     lib.louvain_strerror.restype = ctypes.c_char_p
@@ -243,6 +246,20 @@ class Louvain:
 
     def reset(self):
         _check(load_library().louvain_reset(self._ctx), "louvain_reset")
+        self._warm = None
+
+    def set_membership(self, labels):
+        """Warm start: the first pass starts from `labels` (int32 CUDA tensor of n values in
+        [0, n)), kept referenced here until the next reset.  None clears it."""
+        torch = self._torch
+        if labels is not None:
+            if labels.dtype != torch.int32 or not labels.is_cuda or not labels.is_contiguous() \
+                    or labels.numel() != self.n:
+                raise ValueError("labels must be a contiguous int32 CUDA tensor of n values")
+        self._warm = labels
+        _check(load_library().louvain_set_membership(
+            self._ctx, labels.data_ptr() if labels is not None else None),
+            "louvain_set_membership")
 
     # -- the method
     def move(self) -> Tuple[int, float]:

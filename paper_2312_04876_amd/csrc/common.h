@@ -131,7 +131,7 @@ struct DevScalars {
     int32_t mv_count;       // deferred moves of the current round (deterministic mode)
     int32_t running;        // batches: graphs still moving after this iteration (then reset)
     // --- fields above are cleared at the start of every local-moving phase ---
-    int32_t err;            // validation: bit 0 offsets, 1 targets, 2 weights
+    int32_t err;            // validation: bits 0-2 offsets/targets/weights, 3 batch, 4 labels
     int32_t pad1;
     unsigned long long scan_total;
     unsigned long long hub_slices;   // row slices of the hub bin (sum over hubs)

@@ -551,6 +551,35 @@ __global__ __launch_bounds__(64) void k_iter_end(DevScalars *sc, int it, double 
     }
 }
 
+// ---- warm start: the first pass starts from a given partition
+
+// err bit 4 when a label is outside [0, n), or outside its graph's vertex range in a batch.
+__global__ void k_warm_check(int32_t n, const int32_t *labels, const int32_t *gid,
+                             const int32_t *gvb, int32_t *err)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int c = labels[v];
+        bool bad = c < 0 || c >= n;
+        if (!bad && gid) bad = c < gvb[gid[v]] || c >= gvb[gid[v] + 1];
+        if (bad) atomicOr(err, 16);
+    }
+}
+
+// C'[v] = labels[v]; Sigma' and the sizes of that partition (both zero on entry).
+template <typename ST>
+__global__ void k_warm_labels(int32_t n, const int32_t *labels, const ST *K, int32_t *Cp, ST *Sig,
+                              int32_t *size)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int c = labels[v];
+        Cp[v] = c;
+        atomic_add_t<ST>(&Sig[c], K[v]);
+        atomicAdd(&size[c], 1);
+    }
+}
+
 // ---- batches of independent graphs (see BatchArgs)
 
 // gid[v] = graph owning vertex v (the last graph whose first vertex is <= v,
@@ -963,6 +992,23 @@ void launch_iter_end(DevScalars *sc, int it, double tau, hipStream_t s, const Ba
     if (b && b->gid) k_batch_iter_end<<<grid_for(b->G, 256), 256, 0, s>>>(*b, sc, tau);
     k_iter_end<<<1, 64, 0, s>>>(sc, it, tau, b && b->gid ? 1 : 0);
 }
+
+void launch_warm_check(int32_t n, const int32_t *labels, const int32_t *gid, const int32_t *gvb,
+                       int32_t *err, hipStream_t s)
+{
+    if (n > 0) k_warm_check<<<grid_for(n, 256), 256, 0, s>>>(n, labels, gid, gvb, err);
+}
+
+template <typename ST>
+void launch_warm_labels(int32_t n, const int32_t *labels, const ST *K, int32_t *Cp, ST *Sig,
+                        int32_t *size, hipStream_t s)
+{
+    if (n > 0) k_warm_labels<ST><<<grid_for(n, 256), 256, 0, s>>>(n, labels, K, Cp, Sig, size);
+}
+template void launch_warm_labels<int32_t>(int32_t, const int32_t *, const int32_t *, int32_t *,
+                                          int32_t *, int32_t *, hipStream_t);
+template void launch_warm_labels<int64_t>(int32_t, const int32_t *, const int64_t *, int32_t *,
+                                          int64_t *, int32_t *, hipStream_t);
 
 void launch_batch_gid(int32_t n, const int32_t *gvb, int32_t G, int32_t *gid, hipStream_t s)
 {

@@ -169,6 +169,15 @@ void launch_round_end(DevScalars *sc, int it, hipStream_t s);
 void launch_iter_end(DevScalars *sc, int it, double tau, hipStream_t s,
                      const BatchArgs *b = nullptr);
 
+// ----------------------------------------------------------------- warm start
+// err bit 4 for a label outside [0, n) (or outside its graph's range when gid is non-null).
+void launch_warm_check(int32_t n, const int32_t *labels, const int32_t *gid, const int32_t *gvb,
+                       int32_t *err, hipStream_t s);
+// C' = labels, Sigma' and sizes of that partition (Sig and size zero on entry).
+template <typename ST>
+void launch_warm_labels(int32_t n, const int32_t *labels, const ST *K, int32_t *Cp, ST *Sig,
+                        int32_t *size, hipStream_t s);
+
 // ----------------------------------------------------------------- batches
 // gid[v] for a level whose graph g owns vertices [gvb[g], gvb[g+1]).
 void launch_batch_gid(int32_t n, const int32_t *gvb, int32_t G, int32_t *gid, hipStream_t s);

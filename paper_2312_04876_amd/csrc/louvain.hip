@@ -192,6 +192,7 @@ struct louvain_ctx {
     unsigned long long *gsum, *gsig, *gs2;
     int32_t *gst, *giter, *gcomm;
     int glev;                 // which gid/gvb pair the current level uses (0 = input)
+    const int32_t *warm;      // labels the first pass starts from (louvain_set_membership)
     std::vector<double> gq;   // per-graph modularity of the finished run
     int32_t hub_slices;  // row slices of the current level's hubs
     int32_t hub_tslices; // partitions of the current level's hub rows
@@ -382,6 +383,14 @@ int setup_level(louvain_ctx *ctx)
         r.labels = nullptr;
         r.sigma = nullptr;
         launch_row_reduce<C>(b, 0, r, s);
+        CKL();
+    }
+    if (ctx->pass == 0 && ctx->warm) {
+        // warm start: the first pass starts from the caller's partition
+        launch_fill_bytes_zero(ctx->Sig, (int64_t)ctx->L.sb * l.n, s);
+        launch_fill_bytes_zero(ctx->size, 4 * (int64_t)l.n, s);
+        launch_warm_labels<typename C::ST>(l.n, ctx->warm, (const typename C::ST *)ctx->K,
+                                           ctx->Cp, (typename C::ST *)ctx->Sig, ctx->size, s);
         CKL();
     }
     TRY(prof_end(ctx, F_SETUP, ev));
@@ -1087,6 +1096,24 @@ int louvain_init_batch(louvain_ctx **out, int32_t graphs, const int32_t *graph_o
                     workspace_bytes, p, stream);
 }
 
+int louvain_set_membership(louvain_ctx *ctx, const int32_t *labels)
+{
+    if (!ctx) return LOUVAIN_EINVAL;
+    if (ctx->state != S_READY || ctx->pass != 0) return LOUVAIN_ESTATE;
+    if (!labels) {
+        ctx->warm = nullptr;
+        return LOUVAIN_OK;
+    }
+    launch_fill_bytes_zero(&ctx->sc->err, sizeof(int32_t), ctx->s);
+    const BatchArgs b = batch_args(ctx);
+    launch_warm_check(ctx->n, labels, b.gid, b.gvb, &ctx->sc->err, ctx->s);
+    CKL();
+    TRY(read_scalars(ctx));
+    if (ctx->hsc->err) return LOUVAIN_EINVAL;
+    ctx->warm = labels;
+    return LOUVAIN_OK;
+}
+
 int louvain_batch_results(louvain_ctx *ctx, double *modularity, int32_t *communities)
 {
     if (!ctx || ctx->G <= 0) return LOUVAIN_EINVAL;
@@ -1207,6 +1234,7 @@ int louvain_reset(louvain_ctx *ctx)
 {
     if (!ctx) return LOUVAIN_EINVAL;
     reset_state(ctx);
+    ctx->warm = nullptr;
     launch_iota(ctx->top, ctx->n, ctx->s);
     CKL();
     if (ctx->G > 0) {

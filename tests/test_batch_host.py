@@ -33,3 +33,23 @@ def test_batch_sbm_specs_follow_the_recipe():
         dbar = s["p_in"] * ((sz - 1) + 0.02 * (s["n"] - sz))
         assert 8.0 - 1e-9 <= dbar <= 40.0 + 1e-9
     assert graphgen.batch_sbm_specs(8, seed=4) == sp[:8]
+
+
+def test_perturb_deletes_and_inserts_a_share_of_edges():
+    g = graphgen.rmat(10, 8, seed=3)
+    h = graphgen.perturb(g, 0.1, seed=4)
+    assert h.n == g.n
+    # symmetric, sorted rows, no duplicate pairs, positive weights
+    src = np.repeat(np.arange(h.n), np.diff(h.offsets))
+    pairs = set(zip(src.tolist(), h.targets.tolist()))
+    assert all((b, a) in pairs for a, b in pairs)
+    for i in range(h.n):
+        row = h.targets[h.offsets[i]:h.offsets[i + 1]]
+        assert (np.diff(row) > 0).all()
+    assert (h.weights > 0).all()
+    src_g = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    old = set(zip(src_g.tolist(), g.targets.tolist()))
+    m = sum(1 for a, b in old if a < b)
+    kept = sum(1 for a, b in old if a < b and (a, b) in pairs)
+    assert abs((m - kept) - 0.1 * m) <= 0.02 * m + 2   # about a tenth deleted (re-inserts aside)
+    assert graphgen.perturb(g, 0.0).targets.tolist() == g.targets.tolist()

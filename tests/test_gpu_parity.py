@@ -41,19 +41,25 @@ def _isolated(g):
 
 
 def det_parity(csr, round_bits=1, seed=0, max_passes=10, max_iterations=20, prune=True,
-               tolerance=0.01):
-    """Step the GPU deterministic mode pass by pass against the oracle's sync mode."""
+               tolerance=0.01, initial=None):
+    """Step the GPU deterministic mode pass by pass against the oracle's sync mode
+    (warm-started from the labels `initial` when given)."""
     import paper_2312_04876_amd as P
     print("det parity:", csr.name or "graph", csr.n, csr.nnz, "round_bits", round_bits,
           "seed", seed, flush=True)
     g = _og(csr)
     prm = oracle.Params(mode="sync", seed=seed, sample_bits=round_bits, max_passes=max_passes,
                         max_iterations=max_iterations, prune=prune, tolerance=tolerance)
-    memb_o, q_o, recs = oracle.louvain_trace(g, prm)
+    memb_o, q_o, recs = oracle.louvain_trace(g, prm, initial=initial)
     off, tgt, w = to_device(csr)
     ctx = P.Louvain(off, tgt, w, mode="deterministic", seed=seed, round_bits=round_bits,
                     max_passes=max_passes, max_iterations=max_iterations, prune=prune,
                     tolerance=tolerance)
+    labels0 = None
+    if initial is not None:
+        import torch
+        labels0 = torch.from_numpy(np.ascontiguousarray(initial, dtype=np.int32)).cuda()
+        ctx.set_membership(labels0)
     try:
         for k, rec in enumerate(recs):
             it, _dq = ctx.move()
@@ -156,6 +162,35 @@ def big_star(leaves):
 
 def test_det_hub_partition_overflow():
     det_parity(big_star(4_000_000), max_passes=2)
+
+
+def test_det_warm_start():
+    # the first pass starts from a given partition (the dynamic re-run): blocks of a
+    # coarse SBM labelling, a random labelling, and a cold run's own membership on a
+    # perturbed graph
+    rng = np.random.default_rng(17)
+    sbm = graphgen.workload("sbm10k")
+    det_parity(sbm, initial=(np.arange(sbm.n) // 250).astype(np.int32))
+    rm = graphgen.workload("rmat14-16")
+    det_parity(rm, initial=rng.integers(0, rm.n, size=rm.n).astype(np.int32))
+    memb, _, _ = oracle.louvain(_og(rm), oracle.Params(mode="sync"))
+    rm2 = graphgen.rmat(14, 16, seed=3, name="rmat14-16-other")
+    det_parity(rm2, initial=memb.astype(np.int32), round_bits=2, seed=5)
+
+
+def test_warm_start_rejects_bad_labels_and_late_calls():
+    import torch
+    import paper_2312_04876_amd as P
+    csr = graphgen.workload("rmat12-8")
+    ctx = P.Louvain(*to_device(csr), mode="deterministic")
+    bad = torch.full((csr.n,), csr.n, dtype=torch.int32, device="cuda")
+    with pytest.raises(P.LouvainError):
+        ctx.set_membership(bad)
+    ctx.move()
+    ok = torch.zeros(csr.n, dtype=torch.int32, device="cuda")
+    with pytest.raises(P.LouvainError):
+        ctx.set_membership(ok)
+    ctx.close()
 
 
 def test_det_edge_cases():
