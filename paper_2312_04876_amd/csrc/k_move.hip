@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
     constexpr int NG = 4 * GPW;
     // fast mode: community updates pending in LDS, flushed every FL steps
     constexpr int FL = NG >= 64 ? 1 : 64 / NG;
-    constexpr int PLOG2 = NG * FL >= 256 ? 10 : 8;  // >= 4 slots per decided vertex
+    constexpr int PLOG2 = 4 * NG * FL <= 256 ? 8 : (4 * NG * FL <= 512 ? 9 : 10);  // >= 4 slots/vertex
     constexpr int PS = FAST ? 1 << PLOG2 : 1;
     static_assert(!FAST || PS >= 4 * NG * FL, "pending table too small");
     __shared__ ST s_vals[NG * SP];
