@@ -51,16 +51,16 @@ constexpr int BLOCK_THREADS = 512;
 // Hub rows in local moving are not put in HBM hashtables: each round, the
 // (community, weight) pairs of a queued hub's row are counting-sorted into
 // partitions by a hash of the community, and one workgroup per partition
-// folds it in an LDS table of 2^hub_plog2 slots.  Partitions hold about a
-// quarter of that many pairs (so about a quarter of the slots are used), at
-// most HUB_MAXP per hub; a workgroup of the sorting kernels handles
-// HUB_PSLICE entries of a row.
+// folds it in an LDS table of 2^hub_plog2 slots.  Partitions hold about half
+// that many pairs (a table sized to twice its pairs never overflows), at most
+// HUB_MAXP per hub; a workgroup of the sorting kernels handles HUB_PSLICE
+// entries of a row.
 constexpr int HUB_PSLICE = 8192;
 constexpr int HUB_MAXP = 1024;
 template <typename ST>
 __host__ __device__ constexpr int hub_plog2() { return 12; }
 template <typename ST>
-__host__ __device__ constexpr int hub_part_pairs() { return 1 << (hub_plog2<ST>() - 2); }
+__host__ __device__ constexpr int hub_part_pairs() { return 1 << (hub_plog2<ST>() - 1); }
 // Partitions of a hub row of d entries.
 template <typename ST>
 __host__ __device__ inline int hub_parts(int64_t d)
