@@ -22,7 +22,10 @@ Parity pins live in ``tests/test_oracle_*.py``.  The synchronous iteration
 (``mode="sync"``) is not in the paper; its semantics (hashed rounds, each
 deciding against the state at the start of the round, min-label rule for
 singleton-to-singleton moves) are pinned only by hand-worked cases and
-invariants: parity unpinned beyond those.
+invariants: parity unpinned beyond those.  The colour-ordered iteration
+(``mode="colour"``, one synchronous round per colour class of a greedy colouring
+in hashed priority order) is pinned by the colouring's defining properties, a
+hand-worked case and its reduction to the sequential sweep on a clique.
 """
 from __future__ import annotations
 
@@ -30,7 +33,7 @@ import ctypes
 import os
 import subprocess
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -40,7 +43,8 @@ _LIB = os.path.join(_HERE, "liblouvain_oracle.so")
 
 SYNC = 0
 SEQ = 1
-_MODES = {"sync": SYNC, "seq": SEQ}
+COLOUR = 2
+_MODES = {"sync": SYNC, "seq": SEQ, "colour": COLOUR}
 
 
 def build(force: bool = True) -> str:
@@ -84,6 +88,11 @@ def _load():
         lib.oracle_louvain.restype = i32
         lib.oracle_louvain.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, u64, i32, i32, vp,
                                        vp, vp, vp, vp, vp, vp, vp]
+        lib.oracle_colour.restype = i32
+        lib.oracle_colour.argtypes = [i32, vp, vp, u64, i32, vp]
+        lib.oracle_move_coloured.restype = i32
+        lib.oracle_move_coloured.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, i32, dbl,
+                                             i32, vp, i32, vp, vp, vp, vp]
         lib.oracle_louvain_from.restype = i32
         lib.oracle_louvain_from.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, u64, i32, i32,
                                             vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -205,13 +214,25 @@ class MoveTrace:
     processed: List[int] = field(default_factory=list)
 
 
+def colour(g: Graph, seed: int = 0, pass_index: int = 0) -> Tuple[np.ndarray, int]:
+    """Greedy colouring in decreasing hash priority (Jones-Plassmann's result):
+    (colour int32[n], number of colours)."""
+    col = np.zeros(max(g.n, 1), dtype=np.int32)
+    k = _load().oracle_colour(g.n, _p(g.offsets), _p(g.targets), int(seed) & ((1 << 64) - 1),
+                              int(pass_index), _p(col))
+    if k < 0:
+        raise RuntimeError("oracle_colour failed")
+    return col[:g.n].copy(), int(k)
+
+
 def move(g: Graph, st: MoveState, mode: str = "seq", tau: float = 0.01, max_iter: int = 20,
          prune: bool = True, seed: int = 0, pass_index: int = 0,
          sample_bits: int = 1) -> MoveTrace:
     """Alg. 2 (louvainMove) in place on ``st``; returns sweeps run and per-sweep traces.
 
     ``seed``, ``pass_index`` and ``sample_bits`` split a synchronous iteration into
-    2**sample_bits rounds (a hash of the vertex, iteration and pass picks the round)."""
+    2**sample_bits rounds (a hash of the vertex, iteration and pass picks the round).
+    Mode "colour" uses one synchronous round per colour class of ``colour``."""
     m = max(int(max_iter), 1)
     hi = np.zeros(m, dtype=np.int64)
     lo = np.zeros(m, dtype=np.uint64)
@@ -220,11 +241,19 @@ def move(g: Graph, st: MoveState, mode: str = "seq", tau: float = 0.01, max_iter
     for a, dt in ((st.K, np.int64), (st.Sigma, np.int64), (st.C, np.int32), (st.size, np.int32),
                   (st.active, np.uint8)):
         assert a.dtype == dt and a.flags.c_contiguous and a.shape == (g.n,)
-    l = _load().oracle_move(_MODES[mode], g.n, _p(g.offsets), _p(g.targets), _p(g.weights),
-                            _p(st.K), st.W, _p(st.Sigma), _p(st.C), _p(st.size), _p(st.active),
-                            1 if prune else 0, float(tau), int(max_iter),
-                            int(seed) & ((1 << 64) - 1), int(pass_index), int(sample_bits),
-                            _p(hi), _p(lo), _p(mv), _p(pr))
+    if mode == "colour":
+        col, k = colour(g, seed, pass_index)
+        col = np.ascontiguousarray(col if g.n else np.zeros(1, dtype=np.int32))
+        l = _load().oracle_move_coloured(g.n, _p(g.offsets), _p(g.targets), _p(g.weights),
+                                         _p(st.K), st.W, _p(st.Sigma), _p(st.C), _p(st.size),
+                                         _p(st.active), 1 if prune else 0, float(tau),
+                                         int(max_iter), _p(col), k, _p(hi), _p(lo), _p(mv), _p(pr))
+    else:
+        l = _load().oracle_move(_MODES[mode], g.n, _p(g.offsets), _p(g.targets), _p(g.weights),
+                                _p(st.K), st.W, _p(st.Sigma), _p(st.C), _p(st.size),
+                                _p(st.active), 1 if prune else 0, float(tau), int(max_iter),
+                                int(seed) & ((1 << 64) - 1), int(pass_index), int(sample_bits),
+                                _p(hi), _p(lo), _p(mv), _p(pr))
     if l < 0:
         raise RuntimeError("oracle_move failed")
     return MoveTrace(iterations=int(l), sumN=[_join128(hi[k], lo[k]) for k in range(l)],
@@ -273,7 +302,7 @@ class Params:
     tolerance: float = 0.01
     tolerance_drop: float = 10.0
     aggregation_tolerance: float = 0.8
-    seed: int = 0          # synchronous iteration's round hash (not in the paper)
+    seed: int = 0          # round hash / colouring priority (not in the paper)
     sample_bits: int = 1   # a synchronous iteration runs in 2**sample_bits rounds
 
 

@@ -40,11 +40,22 @@
  * round.  Movers mark their rows for the next iteration; the tolerance test
  * sees the gains of all rounds.
  *
+ * Colour-ordered iteration -- the colouring alternative of Section 2, also
+ * not the paper's own choice.  Each pass colours its graph greedily in
+ * decreasing order of a SplitMix64 priority per vertex (counter
+ * 1 << 63 | p << 40 | i under `seed`): the colouring Jones and Plassmann's
+ * parallel algorithm (SIAM J. Sci. Comput. 1993) produces.  Iteration l then
+ * runs one synchronous round per colour class in ascending colour order; no
+ * two vertices of a round are neighbours, so the singleton rule is off.
+ *
  * parity pins: modularity, the move gain, the sequential sweep, renumbering,
  * the community-vertex CSR, aggregation and the whole pass loop are each
  * checked against independent definitions in the CPU test-suite; the
  * synchronous iteration is pinned by hand-worked cases and invariants only
- * (parity unpinned beyond them).
+ * (parity unpinned beyond them); the colouring is pinned by its defining
+ * properties (proper, greedy-minimal in priority order) and the colour-ordered
+ * iteration by its reduction to the sequential sweep when priorities fall
+ * with the vertex id on a clique.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -52,7 +63,7 @@
 
 typedef __int128 i128;
 
-enum { ORACLE_SYNC = 0, ORACLE_SEQ = 1 };
+enum { ORACLE_SYNC = 0, ORACLE_SEQ = 1, ORACLE_COLOUR = 2 };
 
 static void split128(i128 x, int64_t *hi, uint64_t *lo)
 {
@@ -76,6 +87,63 @@ static int32_t sync_round(uint64_t seed, int32_t sample_bits, int32_t p, int32_t
                    (uint64_t)(uint32_t)i;
     uint64_t x = splitmix_mix(seed + (ctr + 1) * 0x9E3779B97F4A7C15ULL);
     return (int32_t)(x >> (64 - sample_bits));
+}
+
+/* Priority of vertex v in pass p for the colouring (distinct for distinct v). */
+static uint64_t colour_priority(uint64_t seed, int32_t p, int32_t v)
+{
+    uint64_t ctr = (1ULL << 63) | ((uint64_t)(uint32_t)p << 40) | (uint64_t)(uint32_t)v;
+    return splitmix_mix(seed + (ctr + 1) * 0x9E3779B97F4A7C15ULL);
+}
+
+typedef struct {
+    uint64_t prio;
+    int32_t v;
+} prio_v;
+
+static int cmp_prio_desc(const void *a, const void *b)
+{
+    uint64_t x = ((const prio_v *)a)->prio, y = ((const prio_v *)b)->prio;
+    return x < y ? 1 : (x > y ? -1 : 0);
+}
+
+/* Greedy colouring in decreasing priority order (the colouring Jones and
+ * Plassmann's parallel algorithm computes): every vertex takes the smallest
+ * colour no higher-priority neighbour has.  Self-loops are ignored.  Returns
+ * the number of colours, or -1 on allocation failure. */
+int32_t oracle_colour(int32_t n, const int64_t *off, const int32_t *tgt, uint64_t seed,
+                      int32_t pass_index, int32_t *colour)
+{
+    size_t m = (size_t)(n > 0 ? n : 1);
+    prio_v *order = (prio_v *)malloc(m * sizeof(prio_v));
+    int32_t *stamp = (int32_t *)malloc((m + 1) * sizeof(int32_t));
+    if (!order || !stamp) {
+        free(order);
+        free(stamp);
+        return -1;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        order[v].prio = colour_priority(seed, pass_index, v);
+        order[v].v = v;
+        colour[v] = -1;
+    }
+    for (size_t c = 0; c <= m; ++c) stamp[c] = -1;
+    qsort(order, (size_t)n, sizeof(prio_v), cmp_prio_desc);
+    int32_t ncol = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        int32_t v = order[k].v;
+        for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+            int32_t u = tgt[e];
+            if (u != v && colour[u] >= 0) stamp[colour[u]] = v;
+        }
+        int32_t c = 0;
+        while (stamp[c] == v) ++c;
+        colour[v] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    free(order);
+    free(stamp);
+    return ncol;
 }
 
 /* K_i = row sums (Alg. 1, vertexWeights); returns W = sum_i K_i. */
@@ -303,18 +371,21 @@ static double iteration_dq(i128 sumN, int64_t W)
  *                     (min-label singleton rule on) and then applies its
  *                     moves; the next iteration's active set is the rows of
  *                     the movers.
+ *   colour != NULL  : synchronous rounds, round r = the vertices of colour r
+ *                     (r < ncolour), singleton rule off.
  * prune = 0 processes every vertex in every sweep.
  * Per-sweep traces (length max_iter, may be NULL): sumN split in hi/lo,
  * number of moves, number of vertices processed.
  * Returns the number of sweeps run (l_i), or -1 on allocation failure.
  */
-int32_t oracle_move(int32_t mode, int32_t n, const int64_t *off,
-                    const int32_t *tgt, const int64_t *w, const int64_t *K,
-                    int64_t W, int64_t *Sig, int32_t *C, int32_t *size,
-                    uint8_t *active, int32_t prune, double tau,
-                    int32_t max_iter, uint64_t seed, int32_t pass_index,
-                    int32_t sample_bits, int64_t *tr_hi, uint64_t *tr_lo,
-                    int32_t *tr_moves, int32_t *tr_processed)
+static int32_t move_impl(int32_t mode, int32_t n, const int64_t *off,
+                         const int32_t *tgt, const int64_t *w, const int64_t *K,
+                         int64_t W, int64_t *Sig, int32_t *C, int32_t *size,
+                         uint8_t *active, int32_t prune, double tau,
+                         int32_t max_iter, uint64_t seed, int32_t pass_index,
+                         int32_t sample_bits, const int32_t *colour, int32_t ncolour,
+                         int64_t *tr_hi, uint64_t *tr_lo,
+                         int32_t *tr_moves, int32_t *tr_processed)
 {
     scan_table t;
     size_t m = (size_t)(n > 0 ? n : 1);
@@ -356,7 +427,9 @@ int32_t oracle_move(int32_t mode, int32_t n, const int64_t *off,
                 for (int64_t e = off[i]; e < off[i + 1]; ++e) active[tgt[e]] = 1;
             }
         } else {
-            int32_t rounds = 1 << (sample_bits > 0 ? sample_bits : 0);
+            /* colour-ordered mode: one round per colour class, so no two
+             * neighbours ever move together and the singleton rule is not needed */
+            int32_t rounds = colour ? ncolour : 1 << (sample_bits > 0 ? sample_bits : 0);
             memset(mark, 0, (size_t)n);
             for (int32_t r = 0; r < rounds; ++r) {
                 memcpy(C0, C, (size_t)n * sizeof(int32_t));
@@ -365,12 +438,13 @@ int32_t oracle_move(int32_t mode, int32_t n, const int64_t *off,
                 int32_t nm = 0;
                 for (int32_t i = 0; i < n; ++i) {
                     if (!active[i]) continue;
-                    if (sync_round(seed, sample_bits, pass_index, it, i) != r) continue;
+                    if ((colour ? colour[i] : sync_round(seed, sample_bits, pass_index, it, i)) != r)
+                        continue;
                     active[i] = 0;
                     ++processed;
                     int32_t c;
                     i128 N;
-                    if (decide(&t, off, tgt, w, K, W, C0, S0, z0, 1, i, &c, &N)) {
+                    if (decide(&t, off, tgt, w, K, W, C0, S0, z0, colour ? 0 : 1, i, &c, &N)) {
                         mv_i[nm] = i;
                         mv_c[nm] = c;
                         mv_N[nm] = N;
@@ -400,6 +474,32 @@ int32_t oracle_move(int32_t mode, int32_t n, const int64_t *off,
     table_free(&t);
     free(C0); free(S0); free(z0); free(mv_i); free(mv_c); free(mv_N); free(mark);
     return l;
+}
+
+int32_t oracle_move(int32_t mode, int32_t n, const int64_t *off,
+                    const int32_t *tgt, const int64_t *w, const int64_t *K,
+                    int64_t W, int64_t *Sig, int32_t *C, int32_t *size,
+                    uint8_t *active, int32_t prune, double tau,
+                    int32_t max_iter, uint64_t seed, int32_t pass_index,
+                    int32_t sample_bits, int64_t *tr_hi, uint64_t *tr_lo,
+                    int32_t *tr_moves, int32_t *tr_processed)
+{
+    return move_impl(mode, n, off, tgt, w, K, W, Sig, C, size, active, prune, tau, max_iter,
+                     seed, pass_index, sample_bits, NULL, 0, tr_hi, tr_lo, tr_moves,
+                     tr_processed);
+}
+
+/* Colour-ordered local moving: synchronous rounds, round r = the vertices of
+ * colour r (colour[i] in [0, ncolour)). */
+int32_t oracle_move_coloured(int32_t n, const int64_t *off, const int32_t *tgt,
+                             const int64_t *w, const int64_t *K, int64_t W, int64_t *Sig,
+                             int32_t *C, int32_t *size, uint8_t *active, int32_t prune,
+                             double tau, int32_t max_iter, const int32_t *colour,
+                             int32_t ncolour, int64_t *tr_hi, uint64_t *tr_lo,
+                             int32_t *tr_moves, int32_t *tr_processed)
+{
+    return move_impl(ORACLE_SYNC, n, off, tgt, w, K, W, Sig, C, size, active, prune, tau,
+                     max_iter, 0, 0, 0, colour, ncolour, tr_hi, tr_lo, tr_moves, tr_processed);
 }
 
 /*
@@ -531,11 +631,12 @@ int32_t oracle_louvain_from(int32_t mode, int32_t max_passes, int32_t max_iter,
     int32_t *Cp = (int32_t *)malloc(m * sizeof(int32_t));
     int32_t *size = (int32_t *)malloc(m * sizeof(int32_t));
     uint8_t *active = (uint8_t *)malloc(m);
+    int32_t *colour = (int32_t *)malloc(m * sizeof(int32_t));
     int32_t *top = membership;
     if (!offA || !tgtA || !wA || !offB || !tgtB || !wB || !K || !Sig || !Cp ||
-        !size || !active) {
+        !size || !active || !colour) {
         free(offA); free(tgtA); free(wA); free(offB); free(tgtB); free(wB);
-        free(K); free(Sig); free(Cp); free(size); free(active);
+        free(K); free(Sig); free(Cp); free(size); free(active); free(colour);
         return -1;
     }
     /* G' <- G (level buffers are copies so that the input stays untouched) */
@@ -571,9 +672,17 @@ int32_t oracle_louvain_from(int32_t mode, int32_t max_passes, int32_t max_iter,
                 size[initial[i]] += 1;
             }
         }
-        int32_t l = oracle_move(mode, ln, loff, ltgt, lw, K, W, Sig, Cp, size,
-                                active, prune, tau, max_iter, seed, p,
-                                sample_bits, NULL, NULL, NULL, NULL);
+        int32_t l;
+        if (mode == ORACLE_COLOUR) {
+            int32_t ncol = oracle_colour(ln, loff, ltgt, seed, p, colour);
+            l = ncol < 0 ? -1
+                         : move_impl(ORACLE_SYNC, ln, loff, ltgt, lw, K, W, Sig, Cp, size, active,
+                                     prune, tau, max_iter, seed, p, sample_bits, colour, ncol,
+                                     NULL, NULL, NULL, NULL);
+        } else {
+            l = move_impl(mode, ln, loff, ltgt, lw, K, W, Sig, Cp, size, active, prune, tau,
+                          max_iter, seed, p, sample_bits, NULL, 0, NULL, NULL, NULL, NULL);
+        }
         if (l < 0) { rc = -1; break; }
         passes = p + 1;
         if (rec_iters) rec_iters[p] = l;
@@ -605,7 +714,7 @@ int32_t oracle_louvain_from(int32_t mode, int32_t max_passes, int32_t max_iter,
         *Q = oracle_modularity(n, off, tgt, w, top);
     }
     free(offA); free(tgtA); free(wA); free(offB); free(tgtB); free(wB);
-    free(K); free(Sig); free(Cp); free(size); free(active);
+    free(K); free(Sig); free(Cp); free(size); free(active); free(colour);
     return rc == 0 ? passes : rc;
 }
 
