@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22")
-    ap.add_argument("--mode", default="fast", choices=["fast", "deterministic"])
+    ap.add_argument("--mode", default="fast", choices=["fast", "deterministic", "coloured"])
     ap.add_argument("--round-bits", type=int, default=1)
     ap.add_argument("--cpu-baseline", default="same",
                     help="workload the oracle is timed on: 'same' (the benchmark workload, "
@@ -544,6 +544,7 @@ def main():
         "iterations": st["iterations"],
         "communities": st["communities"],
         "per_pass_entries": st["entries"],
+        "colours": st["colours"] if args.mode == "coloured" else None,
         "profiled_ms_per_step": prof_sec * 1e3 if prof_sec else None,
         "kernels": sorted(kernels, key=lambda k: -k["ms_per_step"])[:8],
     }

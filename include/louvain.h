@@ -56,7 +56,15 @@ enum {
     LOUVAIN_DETERMINISTIC = 0,
     /* Asynchronous (Section 4.1): the same rounds, but moves are applied as
      * soon as they are decided and later decisions read the live state. */
-    LOUVAIN_FAST = 1
+    LOUVAIN_FAST = 1,
+    /* Colour-ordered synchronous rounds (the vertex-colouring alternative the
+     * paper cites in Section 2): every level is coloured greedily in
+     * decreasing order of a hashed priority of (seed, pass, vertex), the
+     * colouring Jones and Plassmann's parallel algorithm computes, and each
+     * iteration runs one round per colour class in ascending colour order.
+     * No two neighbours share a round, so the singleton rule is off and
+     * round_bits is ignored.  Bit-identical to the oracle's "colour" mode. */
+    LOUVAIN_COLOURED = 2
 };
 
 /* Status codes. */
@@ -79,14 +87,14 @@ enum {
  * no pass limit; the default is 10.
  */
 typedef struct {
-    int32_t mode;                 /* LOUVAIN_DETERMINISTIC or LOUVAIN_FAST */
+    int32_t mode;                 /* LOUVAIN_DETERMINISTIC, LOUVAIN_FAST or LOUVAIN_COLOURED */
     int32_t max_passes;           /* 0 .. LOUVAIN_MAX_PASSES */
     int32_t max_iterations;       /* 1 .. LOUVAIN_MAX_ITERATIONS */
     int32_t prune;                /* 1: vertex pruning (Section 4.1.6); 0: every vertex every iteration */
     double tolerance;             /* initial tau: stop an iteration loop when its delta-Q <= tau (Alg. 2) */
     double tolerance_drop;        /* tau /= tolerance_drop after each pass (Alg. 1 threshold scaling) */
     double aggregation_tolerance; /* stop when |communities| / |vertices| of the level > this (Alg. 1) */
-    uint64_t seed;                /* key of the round hash */
+    uint64_t seed;                /* key of the round hash and of the colouring priority */
     int32_t round_bits;           /* 0 .. 4: 2^round_bits rounds per iteration (default 1) */
     int32_t profile;              /* 1: time every kernel with HIP events (louvain_kernel_stats) */
 } louvain_params;
@@ -102,6 +110,7 @@ typedef struct {
     int64_t moves[LOUVAIN_MAX_PASSES];          /* moves made in each pass */
     int64_t processed[LOUVAIN_MAX_PASSES];      /* vertex visits in each pass */
     int64_t scanned[LOUVAIN_MAX_PASSES];        /* row entries scanned by local moving in each pass */
+    int32_t colours[LOUVAIN_MAX_PASSES];        /* colour classes of each level (LOUVAIN_COLOURED), else 0 */
 } louvain_stats;
 
 /* Timing and algorithmic traffic of one kernel family (profile = 1). */

@@ -15,7 +15,9 @@ LIB_PATH = os.path.join(HERE, "liblouvain.so")
 
 DETERMINISTIC = 0
 FAST = 1
-_MODES = {"deterministic": DETERMINISTIC, "det": DETERMINISTIC, "fast": FAST}
+COLOURED = 2
+_MODES = {"deterministic": DETERMINISTIC, "det": DETERMINISTIC, "fast": FAST,
+          "coloured": COLOURED, "colour": COLOURED}
 
 OK, EINVAL, EOVERFLOW, ENOSPC, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 MAX_PASSES = 64
@@ -53,6 +55,7 @@ class CStats(ctypes.Structure):
         ("moves", ctypes.c_int64 * MAX_PASSES),
         ("processed", ctypes.c_int64 * MAX_PASSES),
         ("scanned", ctypes.c_int64 * MAX_PASSES),
+        ("colours", ctypes.c_int32 * MAX_PASSES),
     ]
 
     def as_dict(self) -> Dict[str, list]:

@@ -140,9 +140,10 @@ struct DevScalars {
     unsigned long long sigma;       // sum of intra-community entries
     unsigned long long s2[2];       // 128-bit sum of Sigma_c^2
     int32_t alive;                  // batches: graphs not stopped after the last aggregation test
-    int32_t pad2;
+    int32_t coloured;               // colouring: vertices coloured so far
     unsigned long long work[16][5]; // algorithmic work counters per kernel family
-    int32_t pad[16];
+    int32_t fcount[3][5];   // colouring: frontier sizes per degree class, three rotating slots
+    int32_t ncol;           // colouring: colours used (max colour + 1)
     // --- per-wavefront counter rows (folded and cleared by the iteration end);
     // not copied back by the host's scalar reads ---
     unsigned long long spread[NSPREAD][SPREAD_W];
@@ -249,6 +250,26 @@ __host__ __device__ inline int round_of(uint64_t seed, int round_bits, int pass,
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     return (int)(z >> (64 - round_bits));
+}
+
+// Mask of the lanes of this wavefront below the calling lane.
+__device__ inline unsigned long long lanes_below()
+{
+    const int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Priority of vertex v (its index within its graph) for the colouring of pass
+// p: the SplitMix64 output for counter (1 << 63 | p << 40 | v) under key seed.
+// Distinct vertices of a pass get distinct priorities (the counter map and
+// the output mix are both one-to-one).
+__host__ __device__ inline uint64_t colour_priority(uint64_t seed, int pass, int v)
+{
+    const uint64_t ctr = (1ull << 63) | ((uint64_t)(uint32_t)pass << 40) | (uint64_t)(uint32_t)v;
+    uint64_t z = seed + (ctr + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
 }
 
 // Index h with start[h] <= k < start[h + 1] in a non-decreasing start[0..n]

@@ -181,12 +181,6 @@ __device__ inline int len_of(const int32_t *off, const int32_t *deg, int v)
 // per-chunk bin counts, one exclusive scan over [bin][chunk], then every chunk
 // writes its rows at its own offsets (no global atomics, deterministic order).
 
-__device__ inline unsigned long long lanes_below()
-{
-    const int lane = threadIdx.x & 63;
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
 // Per-wavefront bin histogram of one round (one row per lane, b < 0 = none):
 // wcnt[wave][bin] = rows of the wavefront in the bin; returns the lane's rank.
 __device__ inline int wave_bin_rank(int b, int32_t (*wcnt)[NBINS])
@@ -388,12 +382,18 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a)
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const int64_t base = (int64_t)blockIdx.x * BIN_CHUNK;
+    // positions binorder[0, nb), or the positions order[q0, q1) of one colour class
+    const int64_t len = a.order ? (int64_t)(a.q1 - a.q0) : (int64_t)a.nb;
     int sel[R];
+    int32_t pos_of[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t p = base + r * 256 + threadIdx.x;
+        const int64_t i = base + r * 256 + threadIdx.x;
         int b = -1;
-        if (p < a.nb) {
+        pos_of[r] = -1;
+        if (i < len) {
+            const int64_t p = a.order ? (int64_t)a.order[a.q0 + i] : i;
+            pos_of[r] = (int32_t)p;
             const int v = a.binorder[p];
             bool act = a.prune ? (a.flags[v] != 0) : true;
             int lv = v;  // index within its graph (a batch numbers each graph from 0)
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a)
             int pos = a.bins.start[b] + run[b] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][b];
             // vertex ids for bins 0-4, binorder positions for hubs (their tables are per position)
-            const int32_t p = (int32_t)(base + r * 256 + threadIdx.x);
+            const int32_t p = pos_of[r];
             a.worklist[pos] = b == NBINS - 1 ? p : a.binorder[p];
         }
         __syncthreads();
@@ -962,7 +962,8 @@ template void launch_sum_squares<int64_t>(const int64_t *, int32_t, unsigned lon
 
 void launch_compact(const CompactArgs &a, hipStream_t s)
 {
-    if (a.nb > 0) k_compact<<<bin_chunks(a.nb), 256, 0, s>>>(a);
+    const int32_t len = a.order ? a.q1 - a.q0 : a.nb;
+    if (len > 0) k_compact<<<bin_chunks(len), 256, 0, s>>>(a);
 }
 
 template <typename ST>

@@ -80,6 +80,50 @@ template <typename ST>
 void launch_sum_squares(const ST *Sig, int32_t n, unsigned long long *acc, hipStream_t s);
 
 // ----------------------------------------------------------------- local moving
+// ----------------------------------------------------------------- colouring
+// Jones and Plassmann's colouring with readiness counters.  While v is
+// uncoloured, colour[v] = -(1 + its uncoloured higher-priority neighbours);
+// a vertex whose count reaches zero joins the next frontier, and a frontier
+// vertex takes the smallest colour none of its (all coloured) higher-priority
+// neighbours holds, then counts itself off its lower-priority neighbours.
+// Rows fall in five degree classes (bins 0, 1, 2, 3-4 and 5-6) worked by 1, 4,
+// 16, 64 and 1024 lanes per vertex; one launch covers all classes, blocks
+// [rblk[q], rblk[q + 1]) taking class q.  A frontier list holds class q at
+// [cstart[q], cstart[q + 1]).
+constexpr int NCLS = 5;
+constexpr int COLOUR_CT = 1024;  // threads per colouring block
+struct ColourArgs {
+    const int32_t *off, *deg, *tgt;
+    const int32_t *binorder;
+    int32_t cstart[NCLS + 1];  // class regions (also the classes' binorder ranges)
+    int32_t rblk[NCLS + 1];    // first block of each class; rblk[NCLS] = grid
+    const int32_t *in;         // frontier of this step (vertex ids)
+    const int32_t *in_count;   // per class
+    int32_t *out;              // next frontier
+    int32_t *out_count;        // per class (zero on entry)
+    int32_t *clear_count;      // per class: zeroed for the step after next
+    int32_t *colour;
+    int32_t *ncol;             // raised to max colour + 1
+    int32_t *coloured;         // vertices coloured (summed per block)
+    uint64_t seed;
+    int32_t pass;
+    BatchArgs bt;              // batches: priorities by index within the graph
+};
+// Lanes per vertex of class q.
+constexpr int colour_lanes(int q) { return q == 0 ? 1 : (q == 1 ? 4 : (q == 2 ? 16 : (q == 3 ? 64 : 1024))); }
+// Initialisation over every binned row (binorder positions), then one step.
+void launch_colour_init(const ColourArgs &a, hipStream_t s);
+void launch_colour_step(const ColourArgs &a, hipStream_t s);
+
+// Positions binorder[0, nb) sorted by (colour, bin) into order[0, nb): key
+// k = colour * NBINS + bin, koff = exclusive scan of the key counts
+// (kcount, nkeys + 1 entries; the scan's total in koff[nkeys]), kcur a copy
+// of koff used as fill cursors.  Order within a key is arbitrary.
+void launch_class_count(const int32_t *binorder, int32_t nb, BinInfo bins, const int32_t *colour,
+                        int32_t nkeys, int32_t *kcount, hipStream_t s);
+void launch_class_fill(const int32_t *binorder, int32_t nb, BinInfo bins, const int32_t *colour,
+                       int32_t nkeys, int32_t *kcur, int32_t *order, hipStream_t s);
+
 struct CompactArgs {
     const int32_t *binorder;
     int32_t nb;  // rows in bins (binorder[0..nb))
@@ -88,6 +132,9 @@ struct CompactArgs {
     int32_t prune;
     int32_t round, round_bits, pass, it;
     uint64_t seed;
+    const int32_t *order;   // if set: visit the positions order[q0, q1) (one colour class)
+                            // instead of 0 .. nb - 1
+    int32_t q0, q1;
     int32_t *worklist;  // per bin at bins.start[b]: vertex ids (bins 0-4), binorder positions (hubs)
     int32_t *counts;    // per-bin count of this round (zero on entry)
     uint8_t *hub_act;   // per hub (position - bins.start[NBINS-1]): queued this round

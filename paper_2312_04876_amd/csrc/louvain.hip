@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -33,6 +34,8 @@ struct Layout {
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hstage, hstage_w, wcnt, pk, pw, hsz, hoff, scratch;
     size_t bincnt, binoff, slA, slB, mpre, hub_act, hpart, pcnt, poff;
+    size_t colour, front, corder, kcnt, koff;  // colour-ordered mode
+    int64_t kmax;                              // (colour, bin) keys that fit kcnt / koff
     size_t gid[3], gvb[3], gW, gsum, gst, giter, gcomm, gsig, gs2;  // batches
 };
 
@@ -49,7 +52,10 @@ Layout make_layout(int32_t n, int64_t nnz, int sb, int32_t G = 0)
     const size_t n1 = (size_t)n + 1;
     const size_t z = (size_t)(nnz > 0 ? nnz : 1);
     L.sb = sb;
-    L.scratch_elems = scan_scratch_elems((int64_t)n1);
+    // a greedy colouring with k colours has an edge between every two classes, so
+    // k(k - 1) <= nnz and k <= 1 + sqrt(nnz)
+    L.kmax = (int64_t)NBINS * (2 + (int64_t)std::sqrt((double)z)) + 8;
+    L.scratch_elems = scan_scratch_elems(std::max<int64_t>((int64_t)n1, L.kmax + 1));
     L.scalars = take(sizeof(DevScalars));
     L.Cp = take(4 * n1);
     L.top = take(4 * n1);
@@ -95,6 +101,11 @@ Layout make_layout(int32_t n, int64_t nnz, int sb, int32_t G = 0)
     L.slB = take(4 * (n1 + 1));
     L.mpre = take(4 * (n1 + 1));
     L.hub_act = take(n1);
+    L.colour = take(4 * n1);
+    L.front = take(4 * 2 * n1);
+    L.corder = take(4 * n1);
+    L.kcnt = take(4 * ((size_t)L.kmax + 1));
+    L.koff = take(4 * ((size_t)L.kmax + 1));
     if (G > 0) {
         // batches: graph of each vertex and first vertex of each graph, for the
         // input level (0) and two ping-ponged aggregated levels
@@ -141,6 +152,7 @@ enum Fam {
     F_SETUP,
     F_AGGPREP,
     F_FINAL,
+    F_COLOUR,
     F_COUNT
 };
 const char *FAM_NAMES[F_COUNT] = {
@@ -148,8 +160,8 @@ const char *FAM_NAMES[F_COUNT] = {
     "move_bin4_block", "move_bin5_bigblock", "move_bin6_hub", "agg_bin0_8lanes",
     "agg_bin1_32lanes", "agg_bin2_wave", "agg_bin3_wave", "agg_bin4_block",
     "agg_bin5_bigblock", "agg_bin6_hub", "compact", "apply", "iteration_end", "level_setup",
-    "aggregate_prep", "final"};
-static_assert(F_COUNT == 2 * NBINS + 6, "family names");
+    "aggregate_prep", "final", "colour"};
+static_assert(F_COUNT == 2 * NBINS + 7, "family names");
 
 struct Pending {
     int fam;
@@ -185,6 +197,11 @@ struct louvain_ctx {
     void *hpart;
     int32_t *pcnt, *poff;
     uint8_t *hub_act;
+    // colour-ordered mode: colour of each row, frontier lists of the colouring,
+    // rows sorted by (colour, bin), key counts and offsets (device and host)
+    int32_t *colour, *front, *corder, *kcnt, *koff;
+    int32_t ncol;        // colours of the current level
+    std::vector<int32_t> koff_h;
     // batches of independent graphs (G = 0 for a single graph)
     int32_t G;
     int32_t *gid[3], *gvb[3];
@@ -402,6 +419,114 @@ int setup_level(louvain_ctx *ctx)
     return LOUVAIN_OK;
 }
 
+// ---------------------------------------------------------------- colouring
+// Colour the level's rows (Jones-Plassmann frontiers until one is empty), then
+// sort the rows by (colour, bin) and read the key offsets back: round r of an
+// iteration visits order[koff[r * NBINS], koff[(r + 1) * NBINS]).  With
+// symmetric rows the uncoloured vertex of highest priority is always in the
+// frontier, so the frontiers empty exactly when every row is coloured; rows
+// that are not symmetric can leave vertices waiting forever, which is
+// reported as LOUVAIN_EINVAL.
+int colour_level(louvain_ctx *ctx)
+{
+    hipStream_t s = ctx->s;
+    const LevelH &l = ctx->lev;
+    hipEvent_t ev;
+    TRY(prof_begin(ctx, &ev));
+    ColourArgs a;
+    memset(&a, 0, sizeof(a));
+    a.off = l.off;
+    a.deg = l.deg;
+    a.tgt = l.tgt;
+    a.binorder = ctx->binorder;
+    a.colour = ctx->colour;
+    a.ncol = &ctx->sc->ncol;
+    a.coloured = &ctx->sc->coloured;
+    a.seed = ctx->p.seed;
+    a.pass = ctx->pass;
+    a.bt = batch_args(ctx);
+    // degree classes: bins 0, 1, 2, 3-4 and 5-6
+    a.cstart[0] = ctx->bins.start[0];
+    a.cstart[1] = ctx->bins.start[1];
+    a.cstart[2] = ctx->bins.start[2];
+    a.cstart[3] = ctx->bins.start[3];
+    a.cstart[4] = ctx->bins.start[5];
+    a.cstart[5] = ctx->bins.start[NBINS];
+    static_assert(offsetof(DevScalars, ncol) == offsetof(DevScalars, fcount) + 3 * NCLS * sizeof(int32_t),
+                  "ncol follows the frontier counts");
+    // blocks per class for frontiers of the given sizes (at least one per
+    // non-empty class, since a frontier can grow between two host reads)
+    auto set_grid = [&](const int32_t *sizes) {
+        int nb = 0;
+        for (int q = 0; q < NCLS; ++q) {
+            a.rblk[q] = nb;
+            const int64_t cls = (int64_t)a.cstart[q + 1] - a.cstart[q];
+            if (cls <= 0) continue;
+            const int per = COLOUR_CT / colour_lanes(q);
+            const int64_t g = ((int64_t)std::min<int64_t>(sizes[q], cls) + per - 1) / per;
+            nb += (int)std::max<int64_t>(1, std::min<int64_t>(g, 256));
+        }
+        a.rblk[NCLS] = nb;
+    };
+    const size_t stride = (size_t)ctx->n + 1;  // each frontier list holds up to nb <= n rows
+    launch_fill_i32(&ctx->sc->fcount[0][0], 0, 3 * NCLS + 1, s);  // counts and ncol
+    launch_fill_i32(&ctx->sc->coloured, 0, 1, s);
+    int32_t est[NCLS];
+    for (int q = 0; q < NCLS; ++q) est[q] = a.cstart[q + 1] - a.cstart[q];
+    set_grid(est);
+    a.out = ctx->front;
+    a.out_count = ctx->sc->fcount[0];
+    launch_colour_init(a, s);
+    CKL();
+    int64_t k = 0;  // steps launched; step k reads list k & 1 and count slot k % 3
+    int group = 8;
+    for (;;) {
+        for (int j = 0; j < group; ++j, ++k) {
+            a.in = ctx->front + (size_t)(k & 1) * stride;
+            a.in_count = ctx->sc->fcount[k % 3];
+            a.out = ctx->front + (size_t)((k + 1) & 1) * stride;
+            a.out_count = ctx->sc->fcount[(k + 1) % 3];
+            a.clear_count = ctx->sc->fcount[(k + 2) % 3];
+            launch_colour_step(a, s);
+        }
+        CKL();
+        CK(hipMemcpyAsync(&ctx->hsc->fcount[0][0], &ctx->sc->fcount[0][0],
+                          (3 * NCLS + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(&ctx->hsc->coloured, &ctx->sc->coloured, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        const int32_t *f = ctx->hsc->fcount[k % 3];  // the frontier the last step produced
+        int64_t total = 0;
+        for (int q = 0; q < NCLS; ++q) total += f[q];
+        if (total == 0) break;
+        set_grid(f);
+        group = total < 4096 ? 32 : 8;
+    }
+    if (ctx->hsc->coloured != ctx->nb) return LOUVAIN_EINVAL;
+    ctx->ncol = ctx->hsc->ncol;
+    const int64_t nkeys = (int64_t)ctx->ncol * NBINS;
+    if (nkeys > ctx->L.kmax) return LOUVAIN_EINVAL;  // excluded by the bound on colours
+    if (nkeys > 0) {
+        launch_fill_i32(ctx->kcnt, 0, nkeys + 1, s);
+        launch_class_count(ctx->binorder, ctx->nb, ctx->bins, ctx->colour, (int32_t)nkeys, ctx->kcnt,
+                           s);
+        launch_exclusive_scan<int32_t, int32_t>(ctx->kcnt, ctx->koff, nkeys, ctx->scratch, nullptr, s);
+        CK(hipMemcpyAsync(ctx->kcnt, ctx->koff, (size_t)nkeys * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, s));
+        launch_class_fill(ctx->binorder, ctx->nb, ctx->bins, ctx->colour, (int32_t)nkeys, ctx->kcnt,
+                          ctx->corder, s);
+        CKL();
+    }
+    ctx->koff_h.assign((size_t)nkeys + 1, 0);
+    if (nkeys > 0)
+        CK(hipMemcpyAsync(ctx->koff_h.data(), ctx->koff, ((size_t)nkeys + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (nkeys > 0 && ctx->koff_h[(size_t)nkeys] != ctx->nb) return LOUVAIN_EINVAL;
+    TRY(prof_end(ctx, F_COLOUR, ev));
+    return LOUVAIN_OK;
+}
+
 // ---------------------------------------------------------------- local moving (Alg. 2)
 template <class C>
 int move_phase(louvain_ctx *ctx)
@@ -411,7 +536,9 @@ int move_phase(louvain_ctx *ctx)
     const LevelH &l = ctx->lev;
     TRY(setup_level<C>(ctx));
     const bool fast = ctx->p.mode == LOUVAIN_FAST;
-    const int rounds = 1 << ctx->p.round_bits;
+    const bool coloured = ctx->p.mode == LOUVAIN_COLOURED;
+    if (coloured) TRY(colour_level(ctx));
+    const int rounds = coloured ? ctx->ncol : 1 << ctx->p.round_bits;
     const int max_it = ctx->p.max_iterations;
     MoveArgs<C> a;
     a.off = l.off;
@@ -444,7 +571,7 @@ int move_phase(louvain_ctx *ctx)
     a.nhubs = bins_of(ctx, NBINS - 1);
     a.done = &ctx->sc->done;
     a.W = ctx->W;
-    a.rule = 1;
+    a.rule = coloured ? 0 : 1;  // min-label singleton rule: only where neighbours share rounds
     a.bt = batch_args(ctx);
     int grid[NBINS], log2s[NBINS];
     for (int b = 0; b < NBINS; ++b) {
@@ -461,14 +588,32 @@ int move_phase(louvain_ctx *ctx)
         uint8_t *nxt = (it & 1) ? ctx->fa : ctx->fb;
         a.flags_next = nxt;
         for (int r = 0; r < rounds; ++r) {
+            int rgrid[NBINS];
+            int32_t cap = ctx->nb;
+            for (int b = 0; b < NBINS; ++b) rgrid[b] = grid[b];
             CompactArgs ca;
+            ca.order = nullptr;
+            ca.q0 = ca.q1 = 0;
+            if (coloured) {
+                // round r: the rows of colour r, per bin from the (colour, bin) key offsets
+                const int32_t *ko = &ctx->koff_h[(size_t)r * NBINS];
+                ca.order = ctx->corder;
+                ca.q0 = ko[0];
+                ca.q1 = ko[NBINS];
+                cap = ca.q1 - ca.q0;
+                for (int b = 0; b < NBINS; ++b) {
+                    const int per = move_rows_per_block(b);
+                    const int64_t g = ((int64_t)ko[b + 1] - ko[b] + per - 1) / per;
+                    rgrid[b] = (int)std::min<int64_t>(g, b >= 4 ? 1024 : 2048);
+                }
+            }
             ca.binorder = ctx->binorder;
             ca.nb = ctx->nb;
             ca.bins = ctx->bins;
             ca.flags = cur;
             ca.prune = ctx->p.prune;
             ca.round = r;
-            ca.round_bits = ctx->p.round_bits;
+            ca.round_bits = coloured ? 0 : ctx->p.round_bits;  // a colour class is the whole round
             ca.pass = ctx->pass;
             ca.it = it;
             ca.seed = ctx->p.seed;
@@ -483,23 +628,23 @@ int move_phase(louvain_ctx *ctx)
             CKL();
             TRY(prof_end(ctx, F_COMPACT, ev));
             for (int b = 0; b < NBINS; ++b) {
-                if (grid[b] <= 0) continue;
+                if (rgrid[b] <= 0) continue;
                 a.list_begin = ctx->bins.start[b];
                 a.count = &ctx->sc->bin_count[b];
                 a.bin = b;
                 TRY(prof_begin(ctx, &ev));
                 if (b < NBINS - 1)
-                    launch_move<C>(b, fast, a, grid[b], log2s[b], s);
+                    launch_move<C>(b, fast, a, rgrid[b], log2s[b], s);
                 else
-                    launch_move_hubs<C>(fast, a, ctx->hub_slices, ctx->hub_tslices, grid[b], ctx->scratch,
-                                        s);
+                    launch_move_hubs<C>(fast, a, ctx->hub_slices, ctx->hub_tslices, rgrid[b],
+                                        ctx->scratch, s);
                 CKL();
                 TRY(prof_end(ctx, F_MOVE0 + b, ev));
             }
             TRY(prof_begin(ctx, &ev));
             if (!fast) {
                 launch_apply<ST>(ctx->mv_v, ctx->mv_c, ctx->mv_d, &ctx->sc->mv_count, ctx->Cp,
-                                 (const ST *)ctx->K, (ST *)ctx->Sig, ctx->size, ctx->nb,
+                                 (const ST *)ctx->K, (ST *)ctx->Sig, ctx->size, cap,
                                  &ctx->sc->done, s);
                 CKL();
             }
@@ -547,6 +692,7 @@ int move_phase(louvain_ctx *ctx)
         ctx->st.moves[P] = mv;
         ctx->st.processed[P] = pr;
         ctx->st.scanned[P] = scn;
+        ctx->st.colours[P] = coloured ? ctx->ncol : 0;
     }
     return LOUVAIN_OK;
 }
@@ -811,7 +957,8 @@ int do_modularity(louvain_ctx *ctx, double *q)
 
 int check_params(const louvain_params *p)
 {
-    if (p->mode != LOUVAIN_DETERMINISTIC && p->mode != LOUVAIN_FAST) return LOUVAIN_EINVAL;
+    if (p->mode != LOUVAIN_DETERMINISTIC && p->mode != LOUVAIN_FAST && p->mode != LOUVAIN_COLOURED)
+        return LOUVAIN_EINVAL;
     if (p->max_passes < 0 || p->max_passes > LOUVAIN_MAX_PASSES) return LOUVAIN_EINVAL;
     if (p->max_iterations < 1 || p->max_iterations > LOUVAIN_MAX_ITERATIONS) return LOUVAIN_EINVAL;
     if (p->round_bits < 0 || p->round_bits > 4) return LOUVAIN_EINVAL;
@@ -1001,6 +1148,11 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->poff = (int32_t *)(b + L.poff);
     ctx->mpre = (int32_t *)(b + L.mpre);
     ctx->hub_act = b + L.hub_act;
+    ctx->colour = (int32_t *)(b + L.colour);
+    ctx->front = (int32_t *)(b + L.front);
+    ctx->corder = (int32_t *)(b + L.corder);
+    ctx->kcnt = (int32_t *)(b + L.kcnt);
+    ctx->koff = (int32_t *)(b + L.koff);
     if (G > 0) {
         for (int k = 0; k < 3; ++k) {
             ctx->gid[k] = (int32_t *)(b + L.gid[k]);

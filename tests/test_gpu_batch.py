@@ -74,6 +74,19 @@ def test_batch_det_equals_each_graph_alone(round_bits):
         assert qs[g] == oracle.modularity(_og(csr), parts[g]), csr.name
 
 
+def test_batch_coloured_equals_each_graph_alone_and_the_oracle():
+    # priorities are hashed from each vertex's index within its own graph, so the
+    # union's colouring restricted to a graph is that graph's own colouring
+    graphs = mixed_graphs()
+    parts, qs, comms = run_batch(graphs, mode="coloured", seed=6)
+    for g, csr in enumerate(graphs):
+        m1, q1 = alone(csr, mode="coloured", seed=6)
+        assert np.array_equal(parts[g], m1), csr.name
+        assert qs[g] == q1, csr.name
+        mo, qo, _ = oracle.louvain(_og(csr), oracle.Params(mode="colour", seed=6))
+        assert np.array_equal(parts[g], mo) and qs[g] == qo, csr.name
+
+
 def test_batch_det_limits_and_reset():
     import paper_2312_04876_amd as P
     graphs = mixed_graphs()

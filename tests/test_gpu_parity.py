@@ -41,18 +41,21 @@ def _isolated(g):
 
 
 def det_parity(csr, round_bits=1, seed=0, max_passes=10, max_iterations=20, prune=True,
-               tolerance=0.01, initial=None):
+               tolerance=0.01, initial=None, coloured=False):
     """Step the GPU deterministic mode pass by pass against the oracle's sync mode
-    (warm-started from the labels `initial` when given)."""
+    (warm-started from the labels `initial` when given); with `coloured`, the
+    colour-ordered mode against the oracle's colour mode."""
     import paper_2312_04876_amd as P
     print("det parity:", csr.name or "graph", csr.n, csr.nnz, "round_bits", round_bits,
-          "seed", seed, flush=True)
+          "seed", seed, "coloured" if coloured else "hashed rounds", flush=True)
     g = _og(csr)
-    prm = oracle.Params(mode="sync", seed=seed, sample_bits=round_bits, max_passes=max_passes,
-                        max_iterations=max_iterations, prune=prune, tolerance=tolerance)
+    prm = oracle.Params(mode="colour" if coloured else "sync", seed=seed, sample_bits=round_bits,
+                        max_passes=max_passes, max_iterations=max_iterations, prune=prune,
+                        tolerance=tolerance)
     memb_o, q_o, recs = oracle.louvain_trace(g, prm, initial=initial)
     off, tgt, w = to_device(csr)
-    ctx = P.Louvain(off, tgt, w, mode="deterministic", seed=seed, round_bits=round_bits,
+    ctx = P.Louvain(off, tgt, w, mode="coloured" if coloured else "deterministic", seed=seed,
+                    round_bits=round_bits,
                     max_passes=max_passes, max_iterations=max_iterations, prune=prune,
                     tolerance=tolerance)
     labels0 = None
@@ -87,6 +90,10 @@ def det_parity(csr, round_bits=1, seed=0, max_passes=10, max_iterations=20, prun
         assert np.array_equal(memb, memb_o)
         assert q == q_o
         assert st["iterations"] == [r.trace.iterations for r in recs]
+        if coloured:
+            want = [oracle.colour(r.level, seed, k)[1] if r.level.nnz else 0
+                    for k, r in enumerate(recs)]
+            assert st["colours"] == want, ("colours", st["colours"], want)
     finally:
         ctx.close()
 
@@ -137,6 +144,24 @@ def hub_graph():
 
 def test_det_hub_bins():
     det_parity(hub_graph())
+
+
+# ----------------------------------------------------------------- colour-ordered mode
+
+@pytest.mark.parametrize("idx", range(6))
+def test_coloured_small(idx):
+    det_parity(list(small_graphs())[idx], coloured=True)
+
+
+@pytest.mark.parametrize("wl,seed", [("sbm10k", 0), ("rmat13-8", 3), ("rmat16-16", 1)])
+def test_coloured_workloads(wl, seed):
+    det_parity(graphgen.workload(wl), seed=seed, coloured=True)
+
+
+def test_coloured_hubs_weights_and_no_prune():
+    det_parity(hub_graph(), coloured=True)
+    det_parity(graphgen.rmat(13, 12, wmax=8, seed=9, name="rmat13w"), prune=False, seed=4,
+               coloured=True)
 
 
 def big_star(leaves):
