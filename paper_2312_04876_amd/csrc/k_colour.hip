@@ -22,10 +22,10 @@ __device__ inline uint64_t prio_of(const ColourArgs &a, int v)
 
 constexpr int CT = COLOUR_CT;
 
-// Degree class of a row: bins 0, 1, 2, 3-4 and 5-6.
+// Degree class of a row: bins 0, 1, 2, 3 and 4-6.
 __device__ inline int degree_class(int d)
 {
-    return d <= 8 ? 0 : (d <= 32 ? 1 : (d <= 128 ? 2 : (d <= 2048 ? 3 : 4)));
+    return d <= 8 ? 0 : (d <= 32 ? 1 : (d <= 128 ? 2 : (d <= 512 ? 3 : 4)));
 }
 
 template <int G>
@@ -204,68 +204,123 @@ __device__ void step_class(const ColourArgs &a, int q, int b, int nblk, int &top
     }
 }
 
-// One step for the frontier rows of class 4 (longer than 2048 entries), a
-// whole block per row; the colours below the row are gathered in an LDS
-// bitmap of 1024 colours per pass.
-__device__ void step_rows(const ColourArgs &a, int q, int b, int nblk, int &top, int &done, uint32_t *bm,
-                          int *red)
+// Smallest colour >= base missing from the LDS bitmap bm of colours
+// [base, base + 1024), or -1 if all are present.  Block-wide; returns the same
+// value to every thread.
+__device__ inline int bitmap_mex(const uint32_t *bm, int base, int *red)
 {
+    if (threadIdx.x < 64) {
+        const uint32_t word = threadIdx.x < 32 ? bm[threadIdx.x] : 0xffffffffu;
+        const unsigned long long m = __ballot(word != 0xffffffffu);
+        if (threadIdx.x == 0) {
+            int r = -1;
+            if (m) {
+                const int wi = __ffsll((long long)m) - 1;
+                r = base + 32 * wi + __builtin_ctz(~bm[wi]);
+            }
+            *red = r;
+        }
+    }
+    __syncthreads();
+    const int c = *red;
+    __syncthreads();
+    return c;
+}
+
+// One step for the frontier rows of class 4 (longer than 512 entries), cut in
+// chunks of CT entries spread over the class's blocks (chunk j of the i-th
+// row goes to block (i + j) mod nblk).  A block gathers the colours its chunks
+// see in an LDS bitmap and ORs it into the row's slot of cbm (32 words, then
+// a chunk counter); the block that counts the last chunk in takes the
+// smallest colour missing from the combined bitmap, rescanning the whole row
+// for colours from 1024 up when all of [0, 1024) are taken, and clears the
+// slot for the next step.  Slot updates are device-scope atomics.
+__device__ void step_chunks(const ColourArgs &a, int b, int nblk, int &top, int &done, uint32_t *bm,
+                            int *red, int32_t *tv, int32_t *tl)
+{
+    constexpr int q = NCLS - 1;
     const int n = a.in_count[q];
     const int32_t *list = a.in + a.cstart[q];
-    for (int64_t i = b; i < n; i += nblk) {
-        const int v = list[i];
-        const uint64_t pv = prio_of(a, v);
-        const int64_t e0 = a.off[v];
-        const int64_t e1 = e0 + row_len(a.off, a.deg, v);
-        int c = -1;
-        for (int base = 0; c < 0; base += 1024) {
+    for (int t0 = 0; t0 < n; t0 += CT) {
+        // the rows of this tile and their lengths, loaded in parallel
+        const int tn = min(CT, n - t0);
+        if ((int)threadIdx.x < tn) {
+            const int v = list[t0 + threadIdx.x];
+            tv[threadIdx.x] = v;
+            tl[threadIdx.x] = row_len(a.off, a.deg, v);
+        }
+        __syncthreads();
+        for (int r = 0; r < tn; ++r) {
+            const int i = t0 + r;
+            const int v = tv[r];
+            const int64_t len = tl[r];
+            const int nch = (int)((len + CT - 1) / CT);
+            const int j0 = ((b - i) % nblk + nblk) % nblk;
+            if (j0 >= nch) continue;  // uniform over the block
+            const uint64_t pv = prio_of(a, v);
+            const int64_t e0 = a.off[v], e1 = e0 + len;
             if (threadIdx.x < 32) bm[threadIdx.x] = 0;
             __syncthreads();
-            for (int64_t eb = e0; eb < e1; eb += CT) {
-                const int64_t e = eb + threadIdx.x;
+            int mine = 0;
+            for (int j = j0; j < nch; j += nblk, ++mine) {
+                const int64_t e = e0 + (int64_t)j * CT + threadIdx.x;
                 bool push = false;
                 int u = -1;
                 if (e < e1) {
                     u = a.tgt[e];
                     if (u != v) {
                         if (prio_of(a, u) > pv) {
-                            const int cu = a.colour[u] - base;
+                            const int cu = a.colour[u];
                             if (cu >= 0 && cu < 1024) atomicOr(&bm[cu >> 5], 1u << (cu & 31));
-                        } else if (base == 0) {
+                        } else {
                             push = atomicAdd(&a.colour[u], 1) == -2;
                         }
                     }
                 }
-                if (base == 0) frontier_push(push, push ? degree_class(row_len(a.off, a.deg, u)) : 0, u, a);
+                frontier_push(push, push ? degree_class(row_len(a.off, a.deg, u)) : 0, u, a);
             }
             __syncthreads();
-            if (threadIdx.x < 64) {
-                const uint32_t word = threadIdx.x < 32 ? bm[threadIdx.x] : 0xffffffffu;
-                const unsigned long long m = __ballot(word != 0xffffffffu);
-                if (threadIdx.x == 0) {
-                    int r = -1;
-                    if (m) {
-                        const int wi = __ffsll((long long)m) - 1;
-                        r = base + 32 * wi + __builtin_ctz(~bm[wi]);
+            uint32_t *g = a.cbm + (size_t)i * 33;
+            if (threadIdx.x < 32 && bm[threadIdx.x]) atomicOr(&g[threadIdx.x], bm[threadIdx.x]);
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) *red = atomicAdd(&g[32], (uint32_t)mine) + (uint32_t)mine == (uint32_t)nch;
+            __syncthreads();
+            const bool last = *red != 0;
+            __syncthreads();
+            if (!last) continue;  // uniform over the block
+            __threadfence();
+            if (threadIdx.x < 32) bm[threadIdx.x] = atomicOr(&g[threadIdx.x], 0u);
+            __syncthreads();
+            int c = bitmap_mex(bm, 0, red);
+            for (int base = 1024; c < 0; base += 1024) {
+                if (threadIdx.x < 32) bm[threadIdx.x] = 0;
+                __syncthreads();
+                for (int64_t e = e0 + threadIdx.x; e < e1; e += CT) {
+                    const int u = a.tgt[e];
+                    if (u != v && prio_of(a, u) > pv) {
+                        const int cu = a.colour[u] - base;
+                        if (cu >= 0 && cu < 1024) atomicOr(&bm[cu >> 5], 1u << (cu & 31));
                     }
-                    *red = r;
                 }
+                __syncthreads();
+                c = bitmap_mex(bm, base, red);
             }
-            __syncthreads();
-            c = *red;
-            __syncthreads();
+            if (threadIdx.x <= 32) atomicExch(&g[threadIdx.x], 0u);
+            if (threadIdx.x == 0) {
+                a.colour[v] = c;
+                ++done;
+            }
+            top = max(top, c + 1);
         }
-        if (threadIdx.x == 0) {
-            a.colour[v] = c;
-            ++done;
-        }
-        top = max(top, c + 1);
+        __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(CT) void k_colour_step(ColourArgs a)
 {
     __shared__ uint32_t bm[32];
+    __shared__ int32_t tv[CT], tl[CT];
     __shared__ int red, s_max, s_done;
     if (threadIdx.x == 0) {
         s_max = 0;
@@ -283,7 +338,7 @@ __global__ __launch_bounds__(CT) void k_colour_step(ColourArgs a)
     case 1: step_class<4, 2>(a, q, b, nblk, top, done); break;
     case 2: step_class<16, 2>(a, q, b, nblk, top, done); break;
     case 3: step_class<64, 4>(a, q, b, nblk, top, done); break;
-    default: step_rows(a, q, b, nblk, top, done, bm, &red); break;
+    default: step_chunks(a, b, nblk, top, done, bm, &red, tv, tl); break;
     }
     if (top) atomicMax(&s_max, top);
     if (done) atomicAdd(&s_done, done);
@@ -366,6 +421,17 @@ void launch_colour_init(const ColourArgs &a, hipStream_t s)
 void launch_colour_step(const ColourArgs &a, hipStream_t s)
 {
     if (a.rblk[NCLS] > 0) k_colour_step<<<a.rblk[NCLS], CT, 0, s>>>(a);
+}
+
+__global__ void k_gather_i32(const int32_t *src, const int32_t *idx, int32_t n, int32_t *dst)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[idx[i]];
+}
+
+void launch_gather_i32(const int32_t *src, const int32_t *idx, int32_t n, int32_t *dst, hipStream_t s)
+{
+    if (n > 0) k_gather_i32<<<(int)std::min<int64_t>(((int64_t)n + 255) / 256, 1024), 256, 0, s>>>(src, idx, n, dst);
 }
 
 void launch_class_count(const int32_t *binorder, int32_t nb, BinInfo bins, const int32_t *colour,

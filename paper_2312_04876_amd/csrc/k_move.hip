@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256) void k_hub_count(MoveArgs<C> a)
     __shared__ int32_t hist[HUB_MAXP];
     if (*a.done) return;
     int h, v, beg, e0, e1, parts, gp0;
-    if (!hub_slice(a, (int)blockIdx.x, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
+    if (!hub_slice(a, (int)blockIdx.x + a.slice_base, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
     for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
     __syncthreads();
     int32_t *stage = a.hstage + a.hoff[h];
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(256) void k_hub_fill(MoveArgs<C> a)
     __shared__ int32_t hist[HUB_MAXP];
     if (*a.done) return;
     int h, v, beg, e0, e1, parts, gp0;
-    if (!hub_slice(a, (int)blockIdx.x, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
+    if (!hub_slice(a, (int)blockIdx.x + a.slice_base, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
     for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
     __syncthreads();
     int32_t *stage = a.hstage + a.hoff[h];
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
     __shared__ uint64_t st_lo[40], st_hi[40];
     __shared__ int s_sp, s_cnt, s_over;
     if (*a.done) return;
-    const int gp = (int)blockIdx.x;
+    const int gp = (int)blockIdx.x + a.part_base;
     const int h = owner_slice(a.htslice, a.nhubs, gp);
     if (!a.hub_act[h]) return;
     const int v = a.binorder[a.list_begin + h];
@@ -890,9 +890,17 @@ void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int3
 {
     typedef typename C::ST ST;
     if (sort_slices <= 0 || parts <= 0 || grid <= 0) return;
-    launch_fill_bytes_zero(a.pcount, 2 * (int64_t)parts * sizeof(int32_t), s);  // pcount, pcur
+    // the launch covers sorting slices [slice_base, + sort_slices) and partitions
+    // [part_base, + parts): all hubs, or the hubs of one colour class
+    const int pb = a.part_base;
+    if (pb == 0 && a.pcur == a.pcount + parts) {
+        launch_fill_bytes_zero(a.pcount + pb, 2 * (int64_t)parts * sizeof(int32_t), s);  // pcount, pcur
+    } else {
+        launch_fill_i32(a.pcount + pb, 0, parts, s);
+        launch_fill_i32(a.pcur + pb, 0, parts, s);
+    }
     k_hub_count<C><<<sort_slices, 256, 0, s>>>(a);
-    launch_exclusive_scan<int32_t, int32_t>(a.pcount, a.poff, parts, scratch, nullptr, s);
+    launch_exclusive_scan<int32_t, int32_t>(a.pcount + pb, a.poff + pb, parts, scratch, nullptr, s);
     k_hub_fill<C><<<sort_slices, 256, 0, s>>>(a);
     const size_t bytes = ((size_t)1 << hub_plog2<ST>()) * (sizeof(ST) + 4);
     if (bytes > 65536) {

@@ -86,8 +86,9 @@ void launch_sum_squares(const ST *Sig, int32_t n, unsigned long long *acc, hipSt
 // a vertex whose count reaches zero joins the next frontier, and a frontier
 // vertex takes the smallest colour none of its (all coloured) higher-priority
 // neighbours holds, then counts itself off its lower-priority neighbours.
-// Rows fall in five degree classes (bins 0, 1, 2, 3-4 and 5-6) worked by 1, 4,
-// 16, 64 and 1024 lanes per vertex; one launch covers all classes, blocks
+// Rows fall in five degree classes (bins 0, 1, 2, 3 and 4-6) worked by 1, 4,
+// 16 and 64 lanes per vertex and, for class 4, by chunks of 1024 entries
+// spread over blocks (initialisation: a block per row); one launch covers all classes, blocks
 // [rblk[q], rblk[q + 1]) taking class q.  A frontier list holds class q at
 // [cstart[q], cstart[q + 1]).
 constexpr int NCLS = 5;
@@ -105,6 +106,8 @@ struct ColourArgs {
     int32_t *colour;
     int32_t *ncol;             // raised to max colour + 1
     int32_t *coloured;         // vertices coloured (summed per block)
+    uint32_t *cbm;             // class 4: per frontier slot a 1024-colour bitmap and a chunk
+                               // counter (33 words, zero between steps)
     uint64_t seed;
     int32_t pass;
     BatchArgs bt;              // batches: priorities by index within the graph
@@ -121,6 +124,8 @@ void launch_colour_step(const ColourArgs &a, hipStream_t s);
 // of koff used as fill cursors.  Order within a key is arbitrary.
 void launch_class_count(const int32_t *binorder, int32_t nb, BinInfo bins, const int32_t *colour,
                         int32_t nkeys, int32_t *kcount, hipStream_t s);
+// dst[i] = src[idx[i]] for i < n.
+void launch_gather_i32(const int32_t *src, const int32_t *idx, int32_t n, int32_t *dst, hipStream_t s);
 void launch_class_fill(const int32_t *binorder, int32_t nb, BinInfo bins, const int32_t *colour,
                        int32_t nkeys, int32_t *kcur, int32_t *order, hipStream_t s);
 
@@ -172,6 +177,7 @@ struct MoveArgs {
     const int32_t *hslice;             // first sorting slice per hub (HUB_PSLICE entries)
     const int32_t *htslice;            // first partition per hub
     const unsigned long long *htslices;  // total partitions
+    int32_t slice_base, part_base;     // first sorting slice and partition of this launch's hubs
     int32_t *pcount, *pcur, *poff;     // pairs per partition, fill cursors, offsets
     int32_t *pk;                       // partitioned pairs (community, weight)
     typename C::ST *pw;

@@ -34,7 +34,7 @@ struct Layout {
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hstage, hstage_w, wcnt, pk, pw, hsz, hoff, scratch;
     size_t bincnt, binoff, slA, slB, mpre, hub_act, hpart, pcnt, poff;
-    size_t colour, front, corder, kcnt, koff;  // colour-ordered mode
+    size_t colour, front, corder, kcnt, koff, cbm;  // colour-ordered mode
     int64_t kmax;                              // (colour, bin) keys that fit kcnt / koff
     size_t gid[3], gvb[3], gW, gsum, gst, giter, gcomm, gsig, gs2;  // batches
 };
@@ -106,6 +106,7 @@ Layout make_layout(int32_t n, int64_t nnz, int sb, int32_t G = 0)
     L.corder = take(4 * n1);
     L.kcnt = take(4 * ((size_t)L.kmax + 1));
     L.koff = take(4 * ((size_t)L.kmax + 1));
+    L.cbm = take(4 * 33 * ((size_t)z / 513 + 1));  // rows longer than 512 entries
     if (G > 0) {
         // batches: graph of each vertex and first vertex of each graph, for the
         // input level (0) and two ping-ponged aggregated levels
@@ -200,8 +201,10 @@ struct louvain_ctx {
     // colour-ordered mode: colour of each row, frontier lists of the colouring,
     // rows sorted by (colour, bin), key counts and offsets (device and host)
     int32_t *colour, *front, *corder, *kcnt, *koff;
+    uint32_t *cbm;
     int32_t ncol;        // colours of the current level
     std::vector<int32_t> koff_h;
+    std::vector<int32_t> hub_sl_h, hub_pt_h;  // first sorting slice / partition per hub (hubs + 1)
     // batches of independent graphs (G = 0 for a single graph)
     int32_t G;
     int32_t *gid[3], *gvb[3];
@@ -341,6 +344,26 @@ const typename C::WT *lev_w(const LevelH &l)
     return (const typename C::WT *)l.w;
 }
 
+// Staging offsets, sorting slices and partitions of the hub rows in binorder
+// order (cursor and ccount are free during moving).
+template <class C>
+int hub_layout(louvain_ctx *ctx)
+{
+    hipStream_t s = ctx->s;
+    const LevelH &l = ctx->lev;
+    const int hubs = bins_of(ctx, NBINS - 1);
+    launch_hub_move_sizes(ctx->binorder, ctx->bins.start[NBINS - 1], ctx->bins.start[NBINS], l.off, l.deg,
+                          (int)sizeof(typename C::ST), ctx->hsz, ctx->cursor, ctx->ccount, s);
+    launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
+    launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->slA, hubs, ctx->scratch,
+                                            &ctx->sc->hub_slices, s);
+    launch_exclusive_scan<int32_t, int32_t>(ctx->ccount, ctx->slB, hubs, ctx->scratch,
+                                            &ctx->sc->hub_tslices, s);
+    launch_fill_u8(ctx->hub_act, 0, hubs, s);
+    CKL();
+    return LOUVAIN_OK;
+}
+
 // ---------------------------------------------------------------- level setup (Alg. 1 per-pass reset)
 template <class C>
 int setup_level(louvain_ctx *ctx)
@@ -372,20 +395,7 @@ int setup_level(louvain_ctx *ctx)
     const int hubs = bins_of(ctx, NBINS - 1);
     ctx->hub_slices = 0;
     ctx->hub_tslices = 0;
-    if (hubs > 0) {
-        // staging offsets, sorting slices and partitions of the hub rows (cursor and
-        // ccount are free during moving)
-        launch_hub_move_sizes(ctx->binorder, ctx->bins.start[NBINS - 1], ctx->bins.start[NBINS],
-                              l.off, l.deg, (int)sizeof(typename C::ST), ctx->hsz, ctx->cursor,
-                              ctx->ccount, s);
-        launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
-        launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->slA, hubs, ctx->scratch,
-                                                &ctx->sc->hub_slices, s);
-        launch_exclusive_scan<int32_t, int32_t>(ctx->ccount, ctx->slB, hubs, ctx->scratch,
-                                                &ctx->sc->hub_tslices, s);
-        launch_fill_u8(ctx->hub_act, 0, hubs, s);
-        CKL();
-    }
+    if (hubs > 0) TRY(hub_layout<C>(ctx));
     for (int b = 0; b < NBINS; ++b) {
         RowArgs<C> r;
         r.off = l.off;
@@ -427,6 +437,7 @@ int setup_level(louvain_ctx *ctx)
 // frontier, so the frontiers empty exactly when every row is coloured; rows
 // that are not symmetric can leave vertices waiting forever, which is
 // reported as LOUVAIN_EINVAL.
+template <class C>
 int colour_level(louvain_ctx *ctx)
 {
     hipStream_t s = ctx->s;
@@ -442,15 +453,16 @@ int colour_level(louvain_ctx *ctx)
     a.colour = ctx->colour;
     a.ncol = &ctx->sc->ncol;
     a.coloured = &ctx->sc->coloured;
+    a.cbm = ctx->cbm;
     a.seed = ctx->p.seed;
     a.pass = ctx->pass;
     a.bt = batch_args(ctx);
-    // degree classes: bins 0, 1, 2, 3-4 and 5-6
+    // degree classes: bins 0, 1, 2, 3 and 4-6
     a.cstart[0] = ctx->bins.start[0];
     a.cstart[1] = ctx->bins.start[1];
     a.cstart[2] = ctx->bins.start[2];
     a.cstart[3] = ctx->bins.start[3];
-    a.cstart[4] = ctx->bins.start[5];
+    a.cstart[4] = ctx->bins.start[4];
     a.cstart[5] = ctx->bins.start[NBINS];
     static_assert(offsetof(DevScalars, ncol) == offsetof(DevScalars, fcount) + 3 * NCLS * sizeof(int32_t),
                   "ncol follows the frontier counts");
@@ -463,7 +475,8 @@ int colour_level(louvain_ctx *ctx)
             const int64_t cls = (int64_t)a.cstart[q + 1] - a.cstart[q];
             if (cls <= 0) continue;
             const int per = COLOUR_CT / colour_lanes(q);
-            const int64_t g = ((int64_t)std::min<int64_t>(sizes[q], cls) + per - 1) / per;
+            int64_t g = ((int64_t)std::min<int64_t>(sizes[q], cls) + per - 1) / per;
+            if (q == NCLS - 1) g = std::max<int64_t>(8, 4 * g);  // chunks of long rows
             nb += (int)std::max<int64_t>(1, std::min<int64_t>(g, 256));
         }
         a.rblk[NCLS] = nb;
@@ -471,6 +484,7 @@ int colour_level(louvain_ctx *ctx)
     const size_t stride = (size_t)ctx->n + 1;  // each frontier list holds up to nb <= n rows
     launch_fill_i32(&ctx->sc->fcount[0][0], 0, 3 * NCLS + 1, s);  // counts and ncol
     launch_fill_i32(&ctx->sc->coloured, 0, 1, s);
+    launch_fill_i32((int32_t *)ctx->cbm, 0, 33 * ((int64_t)a.cstart[NCLS] - a.cstart[NCLS - 1]), s);
     int32_t est[NCLS];
     for (int q = 0; q < NCLS; ++q) est[q] = a.cstart[q + 1] - a.cstart[q];
     set_grid(est);
@@ -504,6 +518,32 @@ int colour_level(louvain_ctx *ctx)
     }
     if (ctx->hsc->coloured != ctx->nb) return LOUVAIN_EINVAL;
     ctx->ncol = ctx->hsc->ncol;
+    const int hubs = bins_of(ctx, NBINS - 1);
+    if (hubs > 0) {
+        // order the hubs by colour (stable), so that each colour's hubs are
+        // consecutive and a round launches the hub kernels over their slices only
+        int32_t *hub_ids = ctx->binorder + ctx->bins.start[NBINS - 1];
+        std::vector<int32_t> ids(hubs), col(hubs);
+        launch_gather_i32(ctx->colour, hub_ids, hubs, ctx->mv_v, s);  // mv_v is free until the rounds
+        CKL();
+        CK(hipMemcpyAsync(ids.data(), hub_ids, hubs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(col.data(), ctx->mv_v, hubs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        std::vector<int32_t> idx(hubs);
+        for (int h = 0; h < hubs; ++h) idx[h] = h;
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return col[x] < col[y]; });
+        std::vector<int32_t> sorted(hubs);
+        for (int h = 0; h < hubs; ++h) sorted[h] = ids[idx[h]];
+        CK(hipMemcpyAsync(hub_ids, sorted.data(), hubs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        TRY(hub_layout<C>(ctx));
+        ctx->hub_sl_h.assign((size_t)hubs + 1, 0);
+        ctx->hub_pt_h.assign((size_t)hubs + 1, 0);
+        CK(hipMemcpyAsync(ctx->hub_sl_h.data(), ctx->slA, ((size_t)hubs + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(ctx->hub_pt_h.data(), ctx->slB, ((size_t)hubs + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+    }
     const int64_t nkeys = (int64_t)ctx->ncol * NBINS;
     if (nkeys > ctx->L.kmax) return LOUVAIN_EINVAL;  // excluded by the bound on colours
     if (nkeys > 0) {
@@ -537,7 +577,7 @@ int move_phase(louvain_ctx *ctx)
     TRY(setup_level<C>(ctx));
     const bool fast = ctx->p.mode == LOUVAIN_FAST;
     const bool coloured = ctx->p.mode == LOUVAIN_COLOURED;
-    if (coloured) TRY(colour_level(ctx));
+    if (coloured) TRY(colour_level<C>(ctx));
     const int rounds = coloured ? ctx->ncol : 1 << ctx->p.round_bits;
     const int max_it = ctx->p.max_iterations;
     MoveArgs<C> a;
@@ -572,6 +612,9 @@ int move_phase(louvain_ctx *ctx)
     a.done = &ctx->sc->done;
     a.W = ctx->W;
     a.rule = coloured ? 0 : 1;  // min-label singleton rule: only where neighbours share rounds
+    a.slice_base = 0;
+    a.part_base = 0;
+    int32_t hub0 = 0;  // colour-ordered rounds: first hub (in binorder) of the round's colour
     a.bt = batch_args(ctx);
     int grid[NBINS], log2s[NBINS];
     for (int b = 0; b < NBINS; ++b) {
@@ -590,6 +633,7 @@ int move_phase(louvain_ctx *ctx)
         for (int r = 0; r < rounds; ++r) {
             int rgrid[NBINS];
             int32_t cap = ctx->nb;
+            int32_t hub1 = 0;
             for (int b = 0; b < NBINS; ++b) rgrid[b] = grid[b];
             CompactArgs ca;
             ca.order = nullptr;
@@ -606,6 +650,8 @@ int move_phase(louvain_ctx *ctx)
                     const int64_t g = ((int64_t)ko[b + 1] - ko[b] + per - 1) / per;
                     rgrid[b] = (int)std::min<int64_t>(g, b >= 4 ? 1024 : 2048);
                 }
+                if (r == 0) hub0 = 0;
+                hub1 = hub0 + (ko[NBINS] - ko[NBINS - 1]);
             }
             ca.binorder = ctx->binorder;
             ca.nb = ctx->nb;
@@ -633,11 +679,20 @@ int move_phase(louvain_ctx *ctx)
                 a.count = &ctx->sc->bin_count[b];
                 a.bin = b;
                 TRY(prof_begin(ctx, &ev));
-                if (b < NBINS - 1)
+                if (b < NBINS - 1) {
                     launch_move<C>(b, fast, a, rgrid[b], log2s[b], s);
-                else
+                } else if (!coloured) {
                     launch_move_hubs<C>(fast, a, ctx->hub_slices, ctx->hub_tslices, rgrid[b],
                                         ctx->scratch, s);
+                } else {
+                    // the round's hubs are hubs [hub0, hub1) of the colour-sorted hub bin
+                    a.slice_base = ctx->hub_sl_h[hub0];
+                    a.part_base = ctx->hub_pt_h[hub0];
+                    launch_move_hubs<C>(fast, a, ctx->hub_sl_h[hub1] - a.slice_base,
+                                        ctx->hub_pt_h[hub1] - a.part_base, rgrid[b], ctx->scratch, s);
+                    a.slice_base = 0;
+                    a.part_base = 0;
+                }
                 CKL();
                 TRY(prof_end(ctx, F_MOVE0 + b, ev));
             }
@@ -649,6 +704,7 @@ int move_phase(louvain_ctx *ctx)
                 CKL();
             }
             launch_round_end(ctx->sc, it, s);
+            hub0 = hub1;
             CKL();
             TRY(prof_end(ctx, F_APPLY, ev));
         }
@@ -1153,6 +1209,7 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->corder = (int32_t *)(b + L.corder);
     ctx->kcnt = (int32_t *)(b + L.kcnt);
     ctx->koff = (int32_t *)(b + L.koff);
+    ctx->cbm = (uint32_t *)(b + L.cbm);
     if (G > 0) {
         for (int k = 0; k < 3; ++k) {
             ctx->gid[k] = (int32_t *)(b + L.gid[k]);

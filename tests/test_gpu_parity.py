@@ -158,8 +158,33 @@ def test_coloured_workloads(wl, seed):
     det_parity(graphgen.workload(wl), seed=seed, coloured=True)
 
 
+def test_coloured_more_than_1024_colours():
+    # a clique of 1100 vertices needs 1100 colours: rows above 512 entries are coloured
+    # in chunks whose bitmaps cover 1024 colours, so the last 76 need the rescan
+    det_parity(graphgen.cliques(1, 1100, bridges=[(0, 0)]), seed=2, max_passes=2, coloured=True)
+
+
+def multi_hub_graph():
+    """An R-MAT background with six adjacent centres of 9,000 random neighbours each:
+    several hub rows, all of different colours."""
+    base = graphgen.rmat(14, 8, seed=23)
+    src = np.repeat(np.arange(base.n), np.diff(base.offsets))
+    edges = {(int(a), int(b)) for a, b in zip(src, base.targets) if a < b}
+    rng = np.random.default_rng(24)
+    centres = [11, 222, 3333, 4444, 5555, 16000]
+    for c in centres:
+        for v in rng.choice(base.n, size=9000, replace=False):
+            if int(v) != c:
+                edges.add((min(c, int(v)), max(c, int(v))))
+    for i, c in enumerate(centres):
+        for d in centres[i + 1:]:
+            edges.add((min(c, d), max(c, d)))
+    return graphgen.from_edges(base.n, sorted(edges), name="multihub")
+
+
 def test_coloured_hubs_weights_and_no_prune():
     det_parity(hub_graph(), coloured=True)
+    det_parity(multi_hub_graph(), seed=5, coloured=True)
     det_parity(graphgen.rmat(13, 12, wmax=8, seed=9, name="rmat13w"), prune=False, seed=4,
                coloured=True)
 
