@@ -31,6 +31,7 @@ WORKLOADS = {
               ".57/.19/.19/.05, duplicates merged, unit weights, seed 2",
     "rmat24": "R-MAT scale 24, 64 draws per vertex, weights 1..8 per draw, seed 3",
     "sbm10k": "planted-partition SBM, 10,000 vertices, 100 blocks, p_in .05, p_out .0005",
+    "sbm1m": "planted-partition SBM, 1,000,000 vertices, 1,000 blocks, p_in .015, p_out .000005",
 }
 
 

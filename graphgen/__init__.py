@@ -17,6 +17,8 @@ Workload presets (``workload(name)``) give the shapes the paper's evaluation
 calls for, as seeded synthetic stand-ins (no dataset is read):
 
 * ``sbm10k``  -- 10,000 vertices, 100 equal blocks, p_in 0.05, p_out 0.0005
+* ``sbm1m``   -- 1,000,000 vertices, 1,000 equal blocks, p_in 0.015, p_out 0.000005
+  (about 15 neighbours inside the block and 5 outside)
 * ``rmat22``  -- R-MAT scale 22, 16 draws per vertex, a/b/c/d = .57/.19/.19/.05
 * ``rmat24``  -- R-MAT scale 24, 64 draws per vertex, weights 1..8 per draw
 * ``rmatS-F`` -- R-MAT of scale S and F draws per vertex, same a/b/c/d (small cases)
@@ -330,6 +332,9 @@ def workload(name: str, seed: Optional[int] = None, threads: int = 0) -> CSR:
     if name == "sbm10k":
         return sbm(10000, 100, 0.05, 0.0005, seed=1 if seed is None else seed, threads=threads,
                    name=name)
+    if name == "sbm1m":
+        return sbm(1_000_000, 1000, 0.015, 0.000005, seed=1 if seed is None else seed,
+                   threads=threads, name=name)
     if name == "rmat22":
         return rmat(22, 16, seed=2 if seed is None else seed, threads=threads, name=name)
     if name == "rmat24":

@@ -2,12 +2,13 @@
 
 Calls only the oracle (and the seeded generators for its inputs).  For each
 workload it records the sequential-mode modularity (the quality reference of
-the GPU fast mode) and the synchronous-mode result (membership digest, Q,
-iterations and communities per pass; the bit-exact reference of the GPU
-deterministic mode), plus the spread of sequential-mode Q over random vertex
-relabellings, which calibrates the fast-mode tolerance.
+the GPU fast mode), the synchronous-mode and colour-ordered results
+(membership digest, Q, iterations and communities per pass; the bit-exact
+references of the GPU deterministic and colour-ordered modes), plus the
+spread of sequential-mode Q over random vertex relabellings, which calibrates
+the fast-mode tolerance.
 
-Usage: python tests/golden/make_golden.py [workload ...]
+Usage: python tests/golden/make_golden.py [--only colour] [workload ...]
 """
 import hashlib
 import json
@@ -25,7 +26,7 @@ import graphgen  # noqa: E402
 import oracle  # noqa: E402
 
 OUT = os.path.join(HERE, "reference.json")
-DEFAULT = ["sbm10k", "rmat16-16", "rmat18-16", "rmat22"]
+DEFAULT = ["sbm10k", "rmat16-16", "rmat18-16", "rmat22", "sbm1m"]
 
 
 def digest(memb: np.ndarray) -> str:
@@ -47,9 +48,20 @@ def relabel(csr, perm):
     return oracle.as_graph(off, nt[order].astype(np.int32), csr.weights[order])
 
 
-def run(name: str, spread_orders: int):
+def colour_record(g):
+    t = time.time()
+    memb, q, r = oracle.louvain(g, oracle.Params(mode="colour", seed=0))
+    return {"Q": q, "digest": digest(memb), "passes": r["passes"], "iterations": r["iterations"],
+            "communities": r["communities"], "seed": 0, "seconds": round(time.time() - t, 2)}
+
+
+def run(name: str, spread_orders: int, only=None, old=None):
     csr = graphgen.workload(name)
     g = oracle.as_graph(csr.offsets, csr.targets, csr.weights)
+    if only == "colour":
+        rec = dict(old or {})
+        rec["colour"] = colour_record(g)
+        return rec
     rec = {"n": csr.n, "nnz": csr.nnz, "W": int(csr.weights.sum(dtype=np.int64))}
     t = time.time()
     memb, q, r = oracle.louvain(g, oracle.Params(mode="seq"))
@@ -69,16 +81,20 @@ def run(name: str, spread_orders: int):
         qs.append(q)
     if qs:
         rec["seq_relabel_Q"] = qs
+    rec["colour"] = colour_record(g)
     return rec
 
 
 def main(argv):
+    only = None
+    if argv[:1] == ["--only"]:
+        only, argv = argv[1], argv[2:]
     names = argv or DEFAULT
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
-        orders = 4 if name != "rmat22" else 0
+        orders = 4 if name not in ("rmat22", "sbm1m") else 0
         print("oracle on", name, flush=True)
-        data[name] = run(name, orders)
+        data[name] = run(name, orders, only, data.get(name))
         print(json.dumps(data[name]), flush=True)
         with open(OUT, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)

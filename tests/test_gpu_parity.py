@@ -367,3 +367,20 @@ def test_rmat22_det_full_size(rmat22):
     assert st["communities"] == ref["communities"]
     assert hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest() == ref["digest"]
     assert q == ref["Q"]
+
+
+@pytest.mark.parametrize("wl", ["rmat22", "sbm1m", "rmat18-16", "sbm10k"])
+def test_coloured_full_size_matches_the_stored_oracle_run(wl, rmat22):
+    # the colour-ordered run at the benchmark's size against the oracle's colour
+    # mode on the same input (membership digest, Q, iterations, communities)
+    import paper_2312_04876_amd as P
+    csr = rmat22 if wl == "rmat22" else graphgen.workload(wl)
+    print(wl, "colour-ordered mode", csr.n, csr.nnz, flush=True)
+    off, tgt, w = to_device(csr)
+    memb, q, st = P.louvain(off, tgt, w, mode="coloured", seed=0)
+    memb = memb.cpu().numpy()
+    ref = _golden()[wl]["colour"]
+    assert st["iterations"] == ref["iterations"]
+    assert st["communities"] == ref["communities"]
+    assert hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest() == ref["digest"]
+    assert q == ref["Q"]
