@@ -177,14 +177,22 @@ def copy_probe(mib):
                       "copies": 3}))
 
 
-def run_steps(ctx, memb, steps):
+def run_steps(ctx, memb, steps, per_step=None):
+    """Mean seconds per whole run over `steps` runs (one synchronisation on each side of
+    the timed region); each run's own time is appended to `per_step` if given (a run
+    ends with a host read-back, so timing it alone adds no synchronisation)."""
     import torch
     res = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    last = t0
     for _ in range(steps):
         ctx.reset()
         res = ctx.run(memb)
+        if per_step is not None:
+            now = time.perf_counter()
+            per_step.append(now - last)
+            last = now
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / max(steps, 1), res
 
@@ -471,7 +479,8 @@ def main():
     # timed region 1: the plain path
     ctx = P.Louvain(off, tgt, w, **opts)
     run_steps(ctx, memb, args.warmup)
-    sec, (m, q, st) = run_steps(ctx, memb, args.steps)
+    runs = []
+    sec, (m, q, st) = run_steps(ctx, memb, args.steps, runs)
     ctx.close()
     print("plain: %.3f ms/step Q=%.6f passes=%d iterations=%s" %
           (sec * 1e3, q, st["passes"], st["iterations"]), file=sys.stderr, flush=True)
@@ -546,6 +555,8 @@ def main():
         "communities": st["communities"],
         "per_pass_entries": st["entries"],
         "colours": st["colours"] if args.mode == "coloured" else None,
+        "step_ms": {"median": float(np.median(runs)) * 1e3, "min": min(runs) * 1e3,
+                    "max": max(runs) * 1e3},
         "profiled_ms_per_step": prof_sec * 1e3 if prof_sec else None,
         "kernels": sorted(kernels, key=lambda k: -k["ms_per_step"])[:8],
     }
