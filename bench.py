@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--mode", default="fast", choices=["fast", "deterministic", "coloured"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the hub threshold and hub partition size by timing the candidates "
+                         "on this workload first (paper_2312_04876_amd.autotune)")
     ap.add_argument("--round-bits", type=int, default=1)
     ap.add_argument("--cpu-baseline", default="same",
                     help="workload the oracle is timed on: 'same' (the benchmark workload, "
@@ -232,7 +235,16 @@ def batch_main(args):
     tgt = torch.from_numpy(u.targets).to(dev)
     w = torch.from_numpy(u.weights).to(dev)
     memb = torch.empty(max(u.n, 1), dtype=torch.int32, device=dev)
-    ctx = P.Louvain(off, tgt, w, graph_offsets=go, **opts)
+    uopts = dict(opts)
+    tuned = None
+    if args.autotune:
+        from paper_2312_04876_amd import autotune
+        tuned = autotune.tune(off, tgt, w, graph_offsets=go, runs=2, warmup=1, **opts)
+        uopts.update(autotune.tuned_params(tuned))
+        print("autotune (union): hub_rows %d, hub_part_pairs %d (%.1f s)" %
+              (tuned["hub_rows"], tuned["hub_part_pairs"], tuned["seconds"]), file=sys.stderr,
+              flush=True)
+    ctx = P.Louvain(off, tgt, w, graph_offsets=go, **uopts)
     run_steps(ctx, memb, args.warmup)
     sec_b, (m, _q, st) = run_steps(ctx, memb, args.steps)
     q_b, comm_b = ctx.batch_results()
@@ -273,6 +285,7 @@ def batch_main(args):
         "config": {"workload": "batch%d" % args.batch, "graphs": args.batch, "n": u.n,
                    "nnz": u.nnz, "mode": args.mode, "round_bits": args.round_bits},
         "one_by_one": {"value": u.nnz / sec_s, "ms": sec_s * 1e3},
+        "autotune": tuned,
         "speedup": sec_s / sec_b,
         "max_abs_q_difference": max(dq) if dq else 0.0,
         "identical_q": sum(1 for d in dq if d == 0.0),
@@ -475,6 +488,15 @@ def main():
     w = torch.from_numpy(csr.weights).to(dev)
     memb = torch.empty(csr.n, dtype=torch.int32, device=dev)
     opts = dict(mode=args.mode, round_bits=args.round_bits)
+    tuned = None
+    if args.autotune:
+        from paper_2312_04876_amd import autotune
+        tuned = autotune.tune(off, tgt, w, runs=2, warmup=1, **opts)
+        opts.update(autotune.tuned_params(tuned))
+        print("autotune: hub_rows %d, hub_part_pairs %d (%.1f s; %s)" %
+              (tuned["hub_rows"], tuned["hub_part_pairs"], tuned["seconds"],
+               ", ".join("%d/%d %.2f ms" % (r["hub_rows"], r["hub_part_pairs"], r["ms"])
+                         for r in tuned["table"])), file=sys.stderr, flush=True)
 
     # timed region 1: the plain path
     ctx = P.Louvain(off, tgt, w, **opts)
@@ -554,6 +576,7 @@ def main():
         "iterations": st["iterations"],
         "communities": st["communities"],
         "per_pass_entries": st["entries"],
+        "autotune": tuned,
         "colours": st["colours"] if args.mode == "coloured" else None,
         "step_ms": {"median": float(np.median(runs)) * 1e3, "min": min(runs) * 1e3,
                     "max": max(runs) * 1e3},

@@ -97,6 +97,13 @@ typedef struct {
     uint64_t seed;                /* key of the round hash and of the colouring priority */
     int32_t round_bits;           /* 0 .. 4: 2^round_bits rounds per iteration (default 1) */
     int32_t profile;              /* 1: time every kernel with HIP events (louvain_kernel_stats) */
+    /* Scheduling knobs (results do not depend on them; deterministic modes stay
+     * bit-exact): 0 keeps the built-in choice. */
+    int32_t hub_rows;             /* rows longer than this take the hub path (bin 6); 2048 .. 8192,
+                                     clamped to 4096 when accumulators are 8 bytes wide (default:
+                                     8192, or 4096 when wide) */
+    int32_t hub_part_pairs;       /* pairs per hash partition of a hub row in local moving;
+                                     1024 .. 2048 (default 2048) */
 } louvain_params;
 
 /* Per-pass record of the last louvain_run / louvain_move / louvain_aggregate sequence. */

@@ -41,6 +41,7 @@ class CParams(ctypes.Structure):
         ("tolerance", ctypes.c_double), ("tolerance_drop", ctypes.c_double),
         ("aggregation_tolerance", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("round_bits", ctypes.c_int32), ("profile", ctypes.c_int32),
+        ("hub_rows", ctypes.c_int32), ("hub_part_pairs", ctypes.c_int32),
     ]
 
 
@@ -146,7 +147,7 @@ def _check(code: int, where: str):
 
 def make_params(mode="deterministic", max_passes=10, max_iterations=20, prune=True,
                 tolerance=0.01, tolerance_drop=10.0, aggregation_tolerance=0.8, seed=0,
-                round_bits=1, profile=False) -> CParams:
+                round_bits=1, profile=False, hub_rows=0, hub_part_pairs=0) -> CParams:
     p = CParams()
     load_library().louvain_default_params(ctypes.byref(p))
     p.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
@@ -159,6 +160,8 @@ def make_params(mode="deterministic", max_passes=10, max_iterations=20, prune=Tr
     p.seed = int(seed) & ((1 << 64) - 1)
     p.round_bits = int(round_bits)
     p.profile = 1 if profile else 0
+    p.hub_rows = int(hub_rows)
+    p.hub_part_pairs = int(hub_part_pairs)
     return p
 
 

@@ -353,7 +353,8 @@ int hub_layout(louvain_ctx *ctx)
     const LevelH &l = ctx->lev;
     const int hubs = bins_of(ctx, NBINS - 1);
     launch_hub_move_sizes(ctx->binorder, ctx->bins.start[NBINS - 1], ctx->bins.start[NBINS], l.off, l.deg,
-                          (int)sizeof(typename C::ST), ctx->hsz, ctx->cursor, ctx->ccount, s);
+                          (int)sizeof(typename C::ST), ctx->hsz, ctx->cursor, ctx->ccount, s, HUB_PSLICE,
+                          ctx->p.hub_part_pairs);
     launch_exclusive_scan<int64_t, int64_t>(ctx->hsz, ctx->hoff, hubs, ctx->scratch, nullptr, s);
     launch_exclusive_scan<int32_t, int32_t>(ctx->cursor, ctx->slA, hubs, ctx->scratch,
                                             &ctx->sc->hub_slices, s);
@@ -1018,6 +1019,9 @@ int check_params(const louvain_params *p)
     if (p->max_passes < 0 || p->max_passes > LOUVAIN_MAX_PASSES) return LOUVAIN_EINVAL;
     if (p->max_iterations < 1 || p->max_iterations > LOUVAIN_MAX_ITERATIONS) return LOUVAIN_EINVAL;
     if (p->round_bits < 0 || p->round_bits > 4) return LOUVAIN_EINVAL;
+    if (p->hub_rows != 0 && (p->hub_rows < 2048 || p->hub_rows > LDS_MAX_NARROW)) return LOUVAIN_EINVAL;
+    if (p->hub_part_pairs != 0 && (p->hub_part_pairs < 1024 || p->hub_part_pairs > hub_part_pairs<int64_t>()))
+        return LOUVAIN_EINVAL;
     if (!(p->tolerance_drop > 0.0) || p->aggregation_tolerance != p->aggregation_tolerance ||
         p->tolerance != p->tolerance)
         return LOUVAIN_EINVAL;
@@ -1154,6 +1158,7 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->W = (int64_t)W;
     ctx->wide = W >= (1ull << 31);
     ctx->lds_max = ctx->wide ? LDS_MAX_WIDE : LDS_MAX_NARROW;
+    if (prm.hub_rows) ctx->lds_max = std::min(ctx->lds_max, prm.hub_rows);
     ctx->L = make_layout(n, nnz, ctx->wide ? 8 : 4, G);
     if (workspace_bytes < ctx->L.total) return fail(LOUVAIN_ENOSPC);
     const Layout &L = ctx->L;

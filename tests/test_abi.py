@@ -57,6 +57,14 @@ def test_workspace_size_checks(lib):
     bad = P.make_params(max_iterations=0)
     assert lib.louvain_workspace_size(10, 20, 20, ctypes.byref(bad), ctypes.byref(out)) == \
         P.binding.EINVAL
+    # scheduling knobs: 0 (built-in) or inside the documented ranges
+    for kw, ok in (({"hub_rows": 2048}, True), ({"hub_rows": 8192}, True), ({"hub_rows": 2047}, False),
+                   ({"hub_rows": 8193}, False), ({"hub_part_pairs": 1024}, True),
+                   ({"hub_part_pairs": 2048}, True), ({"hub_part_pairs": 512}, False),
+                   ({"hub_part_pairs": 4096}, False)):
+        prm = P.make_params(**kw)
+        code = lib.louvain_workspace_size(10, 20, 20, ctypes.byref(prm), ctypes.byref(out))
+        assert code == (P.binding.OK if ok else P.binding.EINVAL), kw
 
 
 def test_init_rejects_bad_arguments_without_a_gpu(lib):

@@ -41,7 +41,7 @@ def _isolated(g):
 
 
 def det_parity(csr, round_bits=1, seed=0, max_passes=10, max_iterations=20, prune=True,
-               tolerance=0.01, initial=None, coloured=False):
+               tolerance=0.01, initial=None, coloured=False, **knobs):
     """Step the GPU deterministic mode pass by pass against the oracle's sync mode
     (warm-started from the labels `initial` when given); with `coloured`, the
     colour-ordered mode against the oracle's colour mode."""
@@ -57,7 +57,7 @@ def det_parity(csr, round_bits=1, seed=0, max_passes=10, max_iterations=20, prun
     ctx = P.Louvain(off, tgt, w, mode="coloured" if coloured else "deterministic", seed=seed,
                     round_bits=round_bits,
                     max_passes=max_passes, max_iterations=max_iterations, prune=prune,
-                    tolerance=tolerance)
+                    tolerance=tolerance, **knobs)
     labels0 = None
     if initial is not None:
         import torch
@@ -384,3 +384,37 @@ def test_coloured_full_size_matches_the_stored_oracle_run(wl, rmat22):
     assert st["communities"] == ref["communities"]
     assert hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest() == ref["digest"]
     assert q == ref["Q"]
+
+
+# ----------------------------------------------------------------- scheduling knobs
+
+@pytest.mark.parametrize("knobs", [{"hub_rows": 2048, "hub_part_pairs": 1024},
+                                   {"hub_rows": 4096, "hub_part_pairs": 2048}])
+def test_det_parity_under_other_hub_thresholds(knobs):
+    # the knobs move rows between the workgroup and hub paths; results stay the oracle's
+    det_parity(hub_graph(), **knobs)
+    det_parity(graphgen.workload("rmat16-16"), **knobs)
+    det_parity(multi_hub_graph(), seed=5, coloured=True, **knobs)
+
+
+def test_rmat22_det_full_size_with_every_row_above_2048_on_the_hub_path(rmat22):
+    import paper_2312_04876_amd as P
+    off, tgt, w = to_device(rmat22)
+    memb, q, st = P.louvain(off, tgt, w, mode="deterministic", seed=0, round_bits=1,
+                            hub_rows=2048, hub_part_pairs=1024)
+    ref = _golden()["rmat22"]["sync"]
+    assert hashlib.sha256(memb.cpu().numpy().astype(np.int32).tobytes()).hexdigest() == ref["digest"]
+    assert q == ref["Q"]
+
+
+def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
+    from paper_2312_04876_amd import autotune
+    csr = graphgen.workload("rmat16-16")
+    off, tgt, w = to_device(csr)
+    cache = str(tmp_path / "tuned.json")
+    res = autotune.tune(off, tgt, w, runs=1, warmup=1, cache_path=cache, mode="fast")
+    print("autotune", res["hub_rows"], res["hub_part_pairs"], res["table"], flush=True)
+    assert (res["hub_rows"], res["hub_part_pairs"]) in autotune.candidates(wide=False)
+    assert len(res["table"]) == 6 and not res["cached"]
+    again = autotune.tune(off, tgt, w, cache_path=cache, mode="fast")
+    assert again["cached"] and again["hub_rows"] == res["hub_rows"]
