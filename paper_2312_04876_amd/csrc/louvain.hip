@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -170,6 +171,50 @@ struct Pending {
 };
 
 const char *g_last_hip_error = "no HIP error";
+
+// Pinned host blocks for the scalar read-backs, kept in a process-wide pool:
+// freeing pinned memory synchronises the whole device, which would make
+// contexts created and destroyed next to running ones (a server's batches)
+// wait for every stream.  A block goes back to the pool when its context is
+// destroyed and is reused by the next one; the pool is held until the
+// process ends.
+struct PinnedBlock {
+    DevScalars *hsc;
+    int32_t *done;
+};
+std::mutex g_pinned_mu;
+std::vector<PinnedBlock> g_pinned_pool;
+
+bool pinned_take(PinnedBlock *b)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        if (!g_pinned_pool.empty()) {
+            *b = g_pinned_pool.back();
+            g_pinned_pool.pop_back();
+            return true;
+        }
+    }
+    b->hsc = nullptr;
+    b->done = nullptr;
+    if (hipHostMalloc((void **)&b->hsc, sizeof(DevScalars), hipHostMallocDefault) == hipSuccess &&
+        hipHostMalloc((void **)&b->done, sizeof(int32_t) * (LOUVAIN_MAX_ITERATIONS + 1),
+                      hipHostMallocDefault) == hipSuccess)
+        return true;
+    // allocation failure (rare): give back what was obtained
+    if (b->hsc) (void)hipHostFree(b->hsc);
+    b->hsc = nullptr;
+    b->done = nullptr;
+    return false;
+}
+
+// Both pointers come from one pinned_take.
+void pinned_give(DevScalars *hsc, int32_t *done)
+{
+    if (!hsc || !done) return;
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    g_pinned_pool.push_back(PinnedBlock{hsc, done});
+}
 
 }  // namespace
 
@@ -1132,9 +1177,11 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
         louvain_destroy(ctx);
         return code;
     };
-    if (hipHostMalloc((void **)&ctx->hsc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->pinned_done, sizeof(int32_t) * (LOUVAIN_MAX_ITERATIONS + 1),
-                      hipHostMallocDefault) != hipSuccess ||
+    PinnedBlock pb;
+    const bool pinned = pinned_take(&pb);
+    ctx->hsc = pb.hsc;
+    ctx->pinned_done = pb.done;
+    if (!pinned ||
         hipEventCreateWithFlags(&ctx->it_ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->it_ev[1], hipEventDisableTiming) != hipSuccess) {
         g_last_hip_error = "host-side allocation failed";
@@ -1523,8 +1570,7 @@ void louvain_destroy(louvain_ctx *ctx)
         hipEventDestroy(q.b);
     }
     for (hipEvent_t e : ctx->ev_free) hipEventDestroy(e);
-    if (ctx->hsc) hipHostFree(ctx->hsc);
-    if (ctx->pinned_done) hipHostFree(ctx->pinned_done);
+    pinned_give(ctx->hsc, ctx->pinned_done);
     for (int k = 0; k < 2; ++k)
         if (ctx->it_ev[k]) hipEventDestroy(ctx->it_ev[k]);
     delete ctx;
