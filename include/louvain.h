@@ -294,7 +294,10 @@ int louvain_init_batch(louvain_ctx **ctx, int32_t graphs, const int32_t *graph_o
  */
 int louvain_batch_results(louvain_ctx *ctx, double *modularity, int32_t *communities);
 
-/* Release host-side state (the caller's device buffers are untouched). NULL is a no-op. */
+/* Release host-side state (the caller's device buffers are untouched). NULL is a no-op.
+ * The context's pinned host block (a few KB for scalar read-backs) returns to a
+ * process-wide pool that later contexts reuse; pinned memory is never freed
+ * before the process ends, because freeing it would wait for the whole device. */
 void louvain_destroy(louvain_ctx *ctx);
 
 /* Static description of a status code (for EHIP, of the last HIP error). */
