@@ -1,6 +1,7 @@
 """Helpers of the GPU parity tests: upload CSR graphs, canonical forms of level graphs."""
 import numpy as np
 
+import graphgen
 import oracle
 
 
@@ -43,3 +44,18 @@ def is_valid_partition(memb: np.ndarray) -> bool:
         return True
     k = int(memb.max()) + 1
     return memb.min() == 0 and np.unique(memb).size == k
+
+
+def heavy(csr, seed, wmax=1 << 24, name=""):
+    """The same graph with every undirected edge's weight drawn in [1, wmax]: the total
+    weight W passes 2^31, so the path keeps 64-bit totals, 128-bit scores and 64-bit
+    aggregated weights (and the LDS row limit of 8-byte values)."""
+    rng = np.random.default_rng(seed)
+    src = np.repeat(np.arange(csr.n), np.diff(csr.offsets))
+    keep = src <= csr.targets
+    u, v = src[keep], csr.targets[keep]
+    w = rng.integers(1, wmax + 1, size=len(u))
+    out = graphgen.from_edges(csr.n, list(zip(u.tolist(), v.tolist())), w.tolist(),
+                              name=name or (csr.name + "-heavy"))
+    assert int(out.weights.sum(dtype=np.int64)) >= 1 << 31
+    return out

@@ -11,7 +11,7 @@ import pytest
 
 import graphgen
 import oracle
-from gpu_util import is_valid_partition, to_device
+from gpu_util import heavy, is_valid_partition, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -84,6 +84,21 @@ def test_batch_coloured_equals_each_graph_alone_and_the_oracle():
         assert np.array_equal(parts[g], m1), csr.name
         assert qs[g] == q1, csr.name
         mo, qo, _ = oracle.louvain(_og(csr), oracle.Params(mode="colour", seed=6))
+        assert np.array_equal(parts[g], mo) and qs[g] == qo, csr.name
+
+
+def test_batch_with_wide_totals_equals_each_graph_alone():
+    # heavy graphs push the union's total weight past 2^31, so the whole batch runs with
+    # 64-bit totals; the light graphs in it still equal their own (32-bit) runs
+    graphs = [heavy(graphgen.rmat(11, 8, seed=51), 1), graphgen.sbm(300, 6, 0.2, 0.004, seed=11,
+                                                                    name="sbm300"),
+              heavy(graphgen.sbm(800, 8, 0.05, 0.002, seed=52), 2), graphgen.rmat(10, 8, seed=12)]
+    parts, qs, comms = run_batch(graphs, mode="deterministic")
+    for g, csr in enumerate(graphs):
+        m1, q1 = alone(csr, mode="deterministic")
+        assert np.array_equal(parts[g], m1), csr.name
+        assert qs[g] == q1, csr.name
+        mo, qo, _ = oracle.louvain(_og(csr), oracle.Params(mode="sync"))
         assert np.array_equal(parts[g], mo) and qs[g] == qo, csr.name
 
 

@@ -16,7 +16,7 @@ import pytest
 
 import graphgen
 import oracle
-from gpu_util import canonical, is_valid_partition, same_graph, to_device
+from gpu_util import canonical, heavy, is_valid_partition, same_graph, to_device
 from refs import random_graph
 
 pytestmark = pytest.mark.gpu
@@ -140,6 +140,29 @@ def hub_graph():
     edges += [(0, v) for v in range(1, 10001)]
     edges += [(i, j) for i in range(10100, 10220) for j in range(i + 1, 10220)]
     return graphgen.from_edges(n, edges, name="hub")
+
+
+def test_det_wide_totals():
+    det_parity(heavy(graphgen.rmat(12, 8, seed=41), 1))
+    det_parity(heavy(hub_graph(), 2), round_bits=2, seed=3)
+    det_parity(heavy(graphgen.sbm(3000, 30, 0.03, 0.001, seed=42), 3), prune=False)
+
+
+def test_coloured_wide_totals():
+    det_parity(heavy(hub_graph(), 4), coloured=True, seed=1)
+
+
+def test_fast_wide_totals():
+    import paper_2312_04876_amd as P
+    csr = heavy(graphgen.rmat(13, 8, seed=43), 5)
+    g = _og(csr)
+    off, tgt, w = to_device(csr)
+    memb, q, _ = P.louvain(off, tgt, w, mode="fast")
+    memb = memb.cpu().numpy()
+    assert is_valid_partition(memb)
+    assert q == oracle.modularity(g, memb)
+    _, q_seq, _ = oracle.louvain(g, oracle.Params(mode="seq"))
+    assert abs(q - q_seq) <= 0.01
 
 
 def test_det_hub_bins():
