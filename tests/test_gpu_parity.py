@@ -251,6 +251,40 @@ def test_det_warm_start():
     det_parity(rm2, initial=memb.astype(np.int32), round_bits=2, seed=5)
 
 
+def test_coloured_warm_start():
+    sbm = graphgen.workload("sbm10k")
+    det_parity(sbm, initial=(np.arange(sbm.n) // 250).astype(np.int32), coloured=True, seed=2)
+    rm = graphgen.workload("rmat14-16")
+    memb, _, _ = oracle.louvain(_og(rm), oracle.Params(mode="colour", seed=2))
+    det_parity(graphgen.rmat(14, 16, seed=3, name="rmat14-16-other"), initial=memb.astype(np.int32),
+               coloured=True, seed=2)
+
+
+def test_fast_warm_start_from_the_planted_partition():
+    # fast mode from SBM-10k's planted partition: hardly any vertex moves in the first
+    # iteration (the sequential oracle moves 3.4% in its first sweep) and the first
+    # pass ends at least as good as the planted partition
+    import paper_2312_04876_amd as P
+    import torch
+    csr = graphgen.workload("sbm10k")
+    g = _og(csr)
+    off, tgt, w = to_device(csr)
+    planted = graphgen.sbm_blocks(csr.n, 100).astype(np.int32)
+    q0 = oracle.modularity(g, planted)
+    ctx = P.Louvain(off, tgt, w, mode="fast", max_passes=1)
+    try:
+        ctx.set_membership(torch.from_numpy(planted).cuda())
+        ctx.move()
+        tr = ctx.move_trace()
+        labels = ctx.level_labels().cpu().numpy()
+        q1 = oracle.modularity(g, labels)
+        print("from the planted partition: moves", tr["moves"], "Q", q0, "->", q1, flush=True)
+        assert tr["moves"][0] < 0.08 * csr.n
+        assert q1 >= q0 - 0.002
+    finally:
+        ctx.close()
+
+
 def test_warm_start_rejects_bad_labels_and_late_calls():
     import torch
     import paper_2312_04876_amd as P
