@@ -150,6 +150,30 @@ def test_batch_fast_quality():
             assert qs[g] >= q_seq - 0.01, (csr.name, qs[g], q_seq)
 
 
+def test_batch_fast_quality_on_the_batch_recipe():
+    # fast mode over a union of 128 SBMs of the batch recipe, with 4 rounds per
+    # iteration: every graph stays close to its sequential oracle run (with 2 rounds a
+    # large union lets some graphs collapse to a few communities)
+    u, go, specs = graphgen.batch_sbm(128, seed=4, n_max=20000)
+    graphs = []
+    for g in range(128):
+        a, b = int(go[g]), int(go[g + 1])
+        e0, e1 = int(u.offsets[a]), int(u.offsets[b])
+        graphs.append(graphgen.CSR(b - a, (u.offsets[a:b + 1] - e0).astype(np.int64),
+                                   (u.targets[e0:e1] - a).astype(np.int32), u.weights[e0:e1].copy(),
+                                   "g%d" % g))
+    parts, qs, _ = run_batch(graphs, mode="fast", round_bits=2)
+    seq = []
+    for g, csr in enumerate(graphs):
+        og = _og(csr)
+        assert is_valid_partition(parts[g]) and qs[g] == oracle.modularity(og, parts[g])
+        seq.append(oracle.louvain(og, oracle.Params(mode="seq"))[1])
+    d = np.array(qs) - np.array(seq)
+    print("fast batch vs sequential oracle: worst %.4f, mean %.4f, below 0.01: %d" %
+          (d.min(), d.mean(), int((d < -0.01).sum())), flush=True)
+    assert d.min() >= -0.025 and d.mean() >= -0.005
+
+
 def test_batch_rejects_an_edge_between_graphs():
     import paper_2312_04876_amd as P
     csr = graphgen.from_edges(4, [(0, 1), (1, 2), (2, 3)], name="path")
