@@ -509,9 +509,31 @@ def main():
     run_steps(ctx, memb, args.warmup)
     runs = []
     sec, (m, q, st) = run_steps(ctx, memb, args.steps, runs)
+    # per pass (moving + renumbering + aggregation, Alg. 1), stepped through the C ABI
+    # pass by pass with the host waiting after each: median over the timed runs
+    per_pass = []
+    for _ in range(max(1, min(args.steps, 5))):
+        ctx.reset()
+        times = []
+        while True:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.move()
+            _nc, stop = ctx.aggregate()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            if stop:
+                break
+        per_pass.append(times)
+    pst = ctx.stats()
     ctx.close()
+    npass = min(len(t) for t in per_pass)
+    pass_ms = [float(np.median([t[p] for t in per_pass])) * 1e3 for p in range(npass)]
+    pass_rate = [pst["entries"][p] / (pass_ms[p] * 1e-3) for p in range(min(npass, pst["passes"]))]
     print("plain: %.3f ms/step Q=%.6f passes=%d iterations=%s" %
           (sec * 1e3, q, st["passes"], st["iterations"]), file=sys.stderr, flush=True)
+    print("per pass: %s ms, %s edges/s" % (["%.2f" % x for x in pass_ms], ["%.3g" % x for x in pass_rate]),
+          file=sys.stderr, flush=True)
 
     roofline = None
     kernels = []
@@ -582,6 +604,8 @@ def main():
         "iterations": st["iterations"],
         "communities": st["communities"],
         "per_pass_entries": st["entries"],
+        "per_pass_ms": pass_ms,
+        "per_pass_edges_per_s": pass_rate,
         "autotune": tuned,
         "colours": st["colours"] if args.mode == "coloured" else None,
         "step_ms": {"median": float(np.median(runs)) * 1e3, "min": min(runs) * 1e3,
