@@ -55,9 +55,10 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates the HBM byte "
                          "counters of a profiler against a kernel of known traffic) and exit")
-    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
-                    help="summarise four rocprofv3 --pmc output directories (FETCH_SIZE and "
-                         "WRITE_SIZE of one bench step, then of the copy probe) into --pmc-out")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
+                    help="summarise rocprofv3 --pmc output directories into --pmc-out: FETCH_SIZE "
+                         "and WRITE_SIZE of one bench step, the same of the copy probe, and "
+                         "optionally TCC_ATOMIC_sum + TCC_EA0_ATOMIC_sum of one bench step")
     ap.add_argument("--pmc-out", default=os.path.join(ROOT, "profiles", "rmat22_fast_pmc.json"))
     ap.add_argument("--batch", type=int, default=0, metavar="G",
                     help="only run the batched workload: G planted-partition SBMs of uneven size "
@@ -119,7 +120,8 @@ def pmc_summary(dirs, out):
     """Per-kernel HBM traffic per dispatch from FETCH_SIZE / WRITE_SIZE runs, scaled by what the
     same counters read for the copy probe (bytes actually moved / counter bytes)."""
     import re
-    fetch, write, cfetch, cwrite = (_pmc_rows(d) for d in dirs)
+    fetch, write, cfetch, cwrite = (_pmc_rows(d) for d in dirs[:4])
+    atom = _pmc_rows(dirs[4]) if len(dirs) > 4 else []
 
     def per_kernel(rows, counter):
         acc = {}
@@ -137,10 +139,16 @@ def pmc_summary(dirs, out):
 
     ff, wf = copy_factor(cfetch, "FETCH_SIZE"), copy_factor(cwrite, "WRITE_SIZE")
     f, w = per_kernel(fetch, "FETCH_SIZE"), per_kernel(write, "WRITE_SIZE")
+    # L2 atomic requests and those forwarded to the memory side (counts, not KiB)
+    a_l2 = {k: v[1] / 1024.0 for k, v in per_kernel(atom, "TCC_ATOMIC_sum").items()}
+    a_ea = {k: v[1] / 1024.0 for k, v in per_kernel(atom, "TCC_EA0_ATOMIC_sum").items()}
     kernels = {}
     for name in f:
         kernels[name] = {"dispatches": f[name][0], "fetch_bytes": f[name][1] * ff,
                          "write_bytes": w.get(name, [0, 0.0])[1] * wf}
+        if atom:
+            kernels[name]["atomics"] = a_l2.get(name, 0.0)
+            kernels[name]["atomics_memory_side"] = a_ea.get(name, 0.0)
     fam = {}
     for family, pats in FAMILY_KERNELS.items():
         ks = [k for k in kernels if any(re.search(p, k) for p in pats)]
@@ -150,6 +158,11 @@ def pmc_summary(dirs, out):
         launches = sum(kernels[k]["dispatches"] for k in main)
         total = sum(kernels[k]["fetch_bytes"] + kernels[k]["write_bytes"] for k in ks)
         fam[family] = {"launches": launches, "bytes_per_launch": total / max(launches, 1)}
+        if atom:
+            fam[family]["atomics_per_launch"] = sum(kernels[k].get("atomics", 0.0)
+                                                    for k in ks) / max(launches, 1)
+            fam[family]["memory_side_atomics_per_launch"] = sum(
+                kernels[k].get("atomics_memory_side", 0.0) for k in ks) / max(launches, 1)
     data = {"sources_sha256": sources_digest(), "fetch_factor": ff, "write_factor": wf,
             "families": fam, "kernels": kernels}
     with open(out, "w") as fh:
@@ -157,15 +170,16 @@ def pmc_summary(dirs, out):
     print(json.dumps({"fetch_factor": ff, "write_factor": wf, "families": fam}, indent=1))
 
 
-def measured_traffic(family, path):
-    """HBM bytes per launch of `family` from the PMC summary, if it was taken on these sources."""
+def measured_traffic(family, path, key="bytes_per_launch"):
+    """HBM bytes (or, with key, another per-launch figure) of `family` from the PMC summary,
+    if it was taken on these sources."""
     if not os.path.exists(path):
         return None
     data = json.load(open(path))
     if data.get("sources_sha256") != sources_digest():
         return None
     f = data.get("families", {}).get(family)
-    return f["bytes_per_launch"] if f else None
+    return f.get(key) if f else None
 
 
 def copy_probe(mib):
@@ -470,6 +484,9 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.pmc_summary:
+        if len(args.pmc_summary) not in (4, 5):
+            print("--pmc-summary takes 4 or 5 directories", file=sys.stderr)
+            sys.exit(2)
         pmc_summary(args.pmc_summary, args.pmc_out)
         return
     if args.gpus != 1:
@@ -556,13 +573,18 @@ def main():
         dom = max(hot, key=lambda k: k["ms_per_step"])
         gbs = dom["bytes_per_step"] / (dom["ms_per_step"] * 1e-3) / 1e9 if dom["ms_per_step"] else 0.0
         traffic = measured_traffic(dom["name"], args.pmc_out) if args.workload == "rmat22" else None
+        atomics = measured_traffic(dom["name"], args.pmc_out, "atomics_per_launch") \
+            if args.workload == "rmat22" else None
+        per_launch_s = dom["ms_per_step"] * 1e-3 * args.steps / max(dom["launches"], 1)
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["name"],
                     "algorithmic_bytes_per_launch": dom["bytes_per_step"] * args.steps /
                     max(dom["launches"], 1),
                     "launches_per_step": dom["launches"] / args.steps,
                     "ms_per_step": round(dom["ms_per_step"], 4),
-                    "algorithmic_bytes_per_step": dom["bytes_per_step"]}
+                    "algorithmic_bytes_per_step": dom["bytes_per_step"],
+                    "atomics_per_launch": atomics,
+                    "atomics_per_s": atomics / per_launch_s if atomics else None}
         print("profiled: %.3f ms/step" % (prof_sec * 1e3), file=sys.stderr, flush=True)
         for k in sorted(kernels, key=lambda k: -k["ms_per_step"])[:12]:
             print("  %-20s %8.3f ms/step %9.1f GB/s %6d launches" %
