@@ -32,13 +32,15 @@ typedef Cfg<int64_t, int64_t, i128> CfgWide;       // W >= 2^31, aggregated leve
 // ---------------------------------------------------------------------------
 // Degree bins.  A vertex (or, in aggregation, a community with its total
 // member degree) goes to the bin of its row length d:
-//   bin 0: d in [1, 8]        2 lanes per row (4 entries each), 16-slot LDS table
-//   bin 1: d in [9, 32]       8 lanes (4 entries each), 64 slots
-//   bin 2: d in [33, 128]     32 lanes (4 entries each), 256 slots
+//   bin 0: d in [1, 8]        moving: 1 lane per row (up to 8 entries), 16-slot LDS table
+//   bin 1: d in [9, 32]       4 lanes (8 entries each), 64 slots
+//   bin 2: d in [33, 128]     16 lanes (8 entries each), 256 slots
 //   bin 3: d in [129, 512]    one wavefront (8 entries per lane), 1024 slots
+//                             (aggregation: 8 and 32 lanes for bins 0-1, a wavefront for 2-3)
 //   bin 4: d in [513, 2048]   one 256-thread workgroup, up to 4096 LDS slots
 //   bin 5: d in [2049, L]     one 512-thread workgroup, LDS table of up to 2L slots
-//   bin 6: d > L              hubs: row slices + table in HBM
+//   bin 6: d > L              hubs: pairs counting-sorted into hash partitions, each
+//                             folded by one workgroup in LDS (no HBM tables)
 // L (the LDS row limit) is 8192 with 4-byte table values and 4096 with 8-byte
 // ones, so the bin-5 table fits the 160 KB of LDS a gfx950 workgroup may use.
 // Every table has at least twice as many slots as the row has entries, so

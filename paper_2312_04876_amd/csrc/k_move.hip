@@ -4,9 +4,10 @@
 // over the table (Eq. 2 in exact integers, ties to the lowest community
 // id), and move / mark the row's vertices for the next iteration (pruning).
 //
-// Table placement by bin: groups of 2/8/32/64 lanes with private LDS tables
-// (bins 0-3), one workgroup with an LDS table (bins 4-5), row slices folded in
-// LDS and merged into an HBM table (hubs).  Every lane first loads its share
+// Table placement by bin: groups of 1/4/16/64 lanes with private LDS tables
+// (bins 0-3), one workgroup with an LDS table (bins 4-5), and for hubs the
+// row's (community, weight) pairs counting-sorted into hash partitions that one
+// workgroup each folds in LDS.  Every lane first loads its share
 // of the row (targets, weights, then the communities of the targets) into
 // registers so the independent loads are in flight together, then inserts.
 //

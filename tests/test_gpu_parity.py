@@ -131,7 +131,7 @@ def test_det_weighted_and_no_prune():
 
 
 def hub_graph():
-    """An R-MAT background plus a star whose centre has 10,000 neighbours (HBM-table bin)
+    """An R-MAT background plus a star whose centre has 10,000 neighbours (hub bin)
     and a dense block, so every degree bin is exercised in moving and aggregation."""
     base = graphgen.rmat(14, 8, seed=21)
     src = np.repeat(np.arange(base.n), np.diff(base.offsets))
