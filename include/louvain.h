@@ -300,7 +300,7 @@ int louvain_batch_results(louvain_ctx *ctx, double *modularity, int32_t *communi
  * before the process ends, because freeing it would wait for the whole device. */
 void louvain_destroy(louvain_ctx *ctx);
 
-/* Static description of a status code (for EHIP, of the last HIP error). */
+/* Static description of a status code (for EHIP, of the last HIP error seen by the calling thread). */
 const char *louvain_strerror(int code);
 
 #ifdef __cplusplus

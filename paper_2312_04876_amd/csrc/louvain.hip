@@ -170,7 +170,7 @@ struct Pending {
     hipEvent_t a, b;
 };
 
-const char *g_last_hip_error = "no HIP error";
+thread_local const char *g_last_hip_error = "no HIP error";
 
 // Pinned host blocks for the scalar read-backs, kept in a process-wide pool:
 // freeing pinned memory synchronises the whole device, which would make
