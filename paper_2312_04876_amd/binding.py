@@ -285,6 +285,10 @@ class Louvain:
         torch = self._torch
         if membership is None:
             membership = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        elif membership.dtype != torch.int32 or membership.device != self.device \
+                or not membership.is_contiguous() or membership.numel() < self.n:
+            raise ValueError("membership must be a contiguous int32 tensor of at least n values "
+                             "on the graph's device")
         q = ctypes.c_double(0.0)
         st = CStats()
         _check(load_library().louvain_run(self._ctx, membership.data_ptr(), ctypes.byref(q),

@@ -300,6 +300,26 @@ def test_warm_start_rejects_bad_labels_and_late_calls():
     ctx.close()
 
 
+def test_run_checks_the_membership_buffer():
+    import torch
+    import paper_2312_04876_amd as P
+    csr = graphgen.workload("rmat12-8")
+    ctx = P.Louvain(*to_device(csr), mode="deterministic")
+    for bad in [torch.empty(csr.n - 1, dtype=torch.int32, device="cuda"),
+                torch.empty(csr.n, dtype=torch.int64, device="cuda"),
+                torch.empty(csr.n, dtype=torch.int32)]:
+        with pytest.raises(ValueError):
+            ctx.run(bad)
+    m1, q1, _ = ctx.run()
+    m1 = m1.cpu().numpy().copy()
+    ctx.reset()
+    big = torch.full((csr.n + 5,), -7, dtype=torch.int32, device="cuda")
+    m2, q2, _ = ctx.run(big)
+    assert np.array_equal(m1, m2.cpu().numpy()) and q1 == q2
+    assert (big[csr.n:].cpu().numpy() == -7).all()
+    ctx.close()
+
+
 def test_det_edge_cases():
     for csr in [graphgen.from_edges(0, [], name="empty"), graphgen.from_edges(1, [], name="one"),
                 graphgen.from_edges(7, [], name="isolated"),
