@@ -353,6 +353,53 @@ __global__ __launch_bounds__(256) void k_row_reduce(RowArgs<C> a)
     }
 }
 
+// Row reductions of the hub bin, split like its local-moving scatter: slice k
+// of hub h (start[h] <= k < start[h + 1]) covers entries
+// [(k - start[h]) * HUB_PSLICE, +HUB_PSLICE) of the row, one workgroup at a
+// time over a grid-strided slice index.  Partial sums are added atomically
+// (integers, so the order does not matter); for OP 0 K' and Sigma' of the
+// hub rows start at zero.
+template <class C, int OP>
+__global__ __launch_bounds__(256) void k_row_reduce_hub(RowArgs<C> a, const int32_t *start,
+                                                        const unsigned long long *nslices)
+{
+    typedef typename C::ST ST;
+    __shared__ int64_t part[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int total = (int)*nslices;
+    unsigned long long acc = 0;
+    for (int k = blockIdx.x; k < total; k += gridDim.x) {
+        const int h = owner_slice(start, a.count, k);
+        const int v = a.binorder[a.begin + h];
+        const int beg = a.off[v];
+        const int d = len_of(a.off, a.deg, v);
+        const int e0 = (k - start[h]) * HUB_PSLICE;
+        const int e1 = min(e0 + HUB_PSLICE, d);
+        const int lv = OP == 1 ? a.labels[v] : 0;
+        int64_t s = 0;
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+            const int64_t x = (int64_t)a.w[beg + e];
+            if (OP == 0 || a.labels[a.tgt[beg + e]] == lv) s += x;
+        }
+        for (int o = 32; o > 0; o >>= 1) s += shfl_xor_t<int64_t>(s, o);
+        if (lane == 0) part[wave] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int64_t t = part[0] + part[1] + part[2] + part[3];
+            if (OP == 0) {
+                if (t) {
+                    atomic_add_t<ST>(&a.K[v], (ST)t);
+                    atomic_add_t<ST>(&a.Sig[v], (ST)t);
+                }
+            } else {
+                acc += (unsigned long long)t;
+            }
+        }
+        __syncthreads();
+    }
+    if (OP == 1 && threadIdx.x == 0 && acc) atomicAdd(a.sigma, acc);
+}
+
 template <typename ST>
 __global__ __launch_bounds__(256) void k_sum_squares(const ST *Sig, int32_t n,
                                                      unsigned long long *acc)
@@ -928,6 +975,13 @@ template <class C>
 void launch_row_reduce(int bin, int op, const RowArgs<C> &a, hipStream_t s)
 {
     if (a.count <= 0) return;
+    if (bin == NBINS - 1 && a.hslice) {
+        if (op == 0)
+            k_row_reduce_hub<C, 0><<<2048, 256, 0, s>>>(a, a.hslice, a.nslices);
+        else
+            k_row_reduce_hub<C, 1><<<2048, 256, 0, s>>>(a, a.hslice, a.nslices);
+        return;
+    }
     const int rows_per_block[NBINS] = {32, 8, 4, 4, 1, 1, 1};
     const int grid = grid_for(a.count, rows_per_block[bin], 4096);
 #define LV_ROW(G)                                                            \

@@ -71,6 +71,10 @@ struct RowArgs {
     typename C::ST *K, *Sig;
     const int32_t *labels;
     unsigned long long *sigma;
+    // hub bin: exclusive prefix of HUB_PSLICE-entry slices per row and its total
+    // (device); null runs one workgroup per hub row
+    const int32_t *hslice;
+    const unsigned long long *nslices;
 };
 template <class C>
 void launch_row_reduce(int bin, int op, const RowArgs<C> &a, hipStream_t s);

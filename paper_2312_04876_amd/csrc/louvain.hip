@@ -455,6 +455,8 @@ int setup_level(louvain_ctx *ctx)
         r.Sig = (typename C::ST *)ctx->Sig;
         r.labels = nullptr;
         r.sigma = nullptr;
+        r.hslice = b == NBINS - 1 ? ctx->slA : nullptr;  // hub_layout above
+        r.nslices = &ctx->sc->hub_slices;
         launch_row_reduce<C>(b, 0, r, s);
         CKL();
     }
@@ -993,6 +995,10 @@ int modularity_t(louvain_ctx *ctx, double *q)
         r.Sig = nullptr;
         r.labels = ctx->Cp;
         r.sigma = &ctx->sc->sigma;
+        // the level's hub layout: from its setup, which an early stop leaves in
+        // place (aggregation rebuilds the slices only after its stop test)
+        r.hslice = b == NBINS - 1 ? ctx->slA : nullptr;
+        r.nslices = &ctx->sc->hub_slices;
         launch_row_reduce<C>(b, 1, r, s);
     }
     launch_sum_squares<ST>((const ST *)ctx->Sig, l.n, ctx->sc->s2, s);
