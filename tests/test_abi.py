@@ -125,3 +125,12 @@ def test_batch_init_rejects_bad_arguments_before_any_kernel(lib):
     assert lib.louvain_init_batch(ctypes.byref(ctx), 0, None, 0, 0, None, None, None, None, 0,
                                   None, None) == P.binding.EINVAL
     assert lib.louvain_batch_results(None, None, None) == P.binding.EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # without the built library the package raises; it never falls back to CPU code
+    from paper_2312_04876_amd import binding
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "liblouvain.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.load_library()
