@@ -134,7 +134,7 @@ struct DevScalars {
     int32_t running;        // batches: graphs still moving after this iteration (then reset)
     // --- fields above are cleared at the start of every local-moving phase ---
     int32_t err;            // validation: bits 0-2 offsets/targets/weights, 3 batch, 4 labels
-    int32_t pad1;
+    int32_t wmax;           // validation: largest input weight
     unsigned long long scan_total;
     unsigned long long hub_slices;   // row slices of the hub bin (sum over hubs)
     unsigned long long hub_tslices;  // table slices of the hub bin

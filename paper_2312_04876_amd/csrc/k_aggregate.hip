@@ -330,16 +330,18 @@ __device__ inline void agg_window(const AggArgs<C> &a, int nh, int k, int *idx, 
 // window's flattened offset (count in wcnt), and adds their count per
 // partition into pcount.  Folding first keeps a community's many entries
 // into the same neighbour (its internal edges above all) to one pair per
-// window.
-template <class C>
+// window.  VT is the table's value type: 32-bit whenever AGG_PSLICE times the
+// largest weight stays below 2^31 (no window sum can overflow), which halves
+// the table of 64-bit configurations and doubles the workgroups per CU.
+template <class C, class VT>
 __global__ __launch_bounds__(256) void k_agg_hub_count(AggArgs<C> a, int32_t nh)
 {
     typedef typename C::ST ST;
     constexpr int LOG2S = AGG_PLOG2 + 1;
     constexpr int S = 1 << LOG2S;
     extern __shared__ __align__(16) unsigned char smem[];
-    ST *vals = (ST *)smem;
-    int32_t *keys = (int32_t *)(smem + (size_t)S * sizeof(ST));
+    VT *vals = (VT *)smem;
+    int32_t *keys = (int32_t *)(smem + (size_t)S * sizeof(VT));
     __shared__ Window W;
     __shared__ int32_t hist[HUB_MAXP];
     __shared__ int s_n;
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(256) void k_agg_hub_count(AggArgs<C> a, int32_t nh)
     if (threadIdx.x == 0) s_n = 0;
     unsigned long long ne_ = 0, nm_ = 0;
     walk_window(a, W, mb, me, base, w0, w1, &nm_, [&](int t, int e) {
-        lds_add<ST>(keys, vals, LOG2S, a.Cp[a.tgt[e]], (ST)a.w[e]);
+        lds_add<VT>(keys, vals, LOG2S, a.Cp[a.tgt[e]], (VT)a.w[e]);
         ++ne_;
     });
     int32_t *sk = a.hstage + base + w0;
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(256) void k_agg_hub_count(AggArgs<C> a, int32_t nh)
         if (key < 0) continue;
         const int i = atomicAdd(&s_n, 1);
         sk[i] = key;
-        sw[i] = vals[q];
+        sw[i] = (ST)vals[q];
         atomicAdd(&hist[part_of(key, parts)], 1);
     }
     __syncthreads();
@@ -531,22 +533,31 @@ void launch_aggregate(int bin, const AggArgs<C> &a, int log2s_max, hipStream_t s
     }
 }
 
+template <class C, class VT>
+void launch_agg_hub_count(const AggArgs<C> &a, int32_t sort_slices, hipStream_t s)
+{
+    const size_t bytes = ((size_t)2 << AGG_PLOG2) * (sizeof(VT) + 4);
+    if (bytes > 32768) {
+        // raise the dynamic-LDS limit of this kernel to what the launch asks for; a
+        // failure shows up as a launch error at the caller's check
+        if (hipFuncSetAttribute((const void *)&k_agg_hub_count<C, VT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+            (void)hipGetLastError();
+    }
+    k_agg_hub_count<C, VT><<<sort_slices, 256, bytes, s>>>(a, a.count);
+}
+
 template <class C>
 void launch_aggregate_hub(const AggArgs<C> &a, int32_t sort_slices, int32_t parts,
-                          int64_t *scratch, hipStream_t s)
+                          int64_t wmax, int64_t *scratch, hipStream_t s)
 {
     if (a.count <= 0 || sort_slices <= 0 || parts <= 0) return;
     typedef typename C::ST ST;
     launch_fill_bytes_zero(a.pcount, 2 * (int64_t)parts * sizeof(int32_t), s);  // pcount, pcur
-    const size_t bytes = ((size_t)2 << AGG_PLOG2) * (sizeof(ST) + 4);
-    if (bytes > 32768) {
-        // raise the dynamic-LDS limit of this kernel to what the launch asks for; a
-        // failure shows up as a launch error at the caller's check
-        if (hipFuncSetAttribute((const void *)&k_agg_hub_count<C>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
-            (void)hipGetLastError();
-    }
-    k_agg_hub_count<C><<<sort_slices, 256, bytes, s>>>(a, a.count);
+    if (sizeof(ST) > 4 && wmax > 0 && wmax * AGG_PSLICE < ((int64_t)1 << 31))
+        launch_agg_hub_count<C, int32_t>(a, sort_slices, s);
+    else
+        launch_agg_hub_count<C, ST>(a, sort_slices, s);
     launch_exclusive_scan<int32_t, int32_t>(a.pcount, a.poff, parts, scratch, nullptr, s);
     k_agg_hub_fill<C><<<sort_slices, 256, 0, s>>>(a, a.count);
     k_agg_hub_part<C><<<parts, 256, 0, s>>>(a, a.count);
@@ -556,10 +567,10 @@ template void launch_aggregate<CfgNarrow>(int, const AggArgs<CfgNarrow> &, int, 
 template void launch_aggregate<CfgWideIn>(int, const AggArgs<CfgWideIn> &, int, hipStream_t);
 template void launch_aggregate<CfgWide>(int, const AggArgs<CfgWide> &, int, hipStream_t);
 template void launch_aggregate_hub<CfgNarrow>(const AggArgs<CfgNarrow> &, int32_t, int32_t,
-                                              int64_t *, hipStream_t);
+                                              int64_t, int64_t *, hipStream_t);
 template void launch_aggregate_hub<CfgWideIn>(const AggArgs<CfgWideIn> &, int32_t, int32_t,
-                                              int64_t *, hipStream_t);
+                                              int64_t, int64_t *, hipStream_t);
 template void launch_aggregate_hub<CfgWide>(const AggArgs<CfgWide> &, int32_t, int32_t,
-                                            int64_t *, hipStream_t);
+                                            int64_t, int64_t *, hipStream_t);
 
 }  // namespace lv

@@ -131,9 +131,11 @@ __global__ void k_iota(int32_t *p, int64_t n)
 
 __global__ __launch_bounds__(256) void k_validate(int32_t n, int64_t nnz, const int32_t *off,
                                                   const int32_t *tgt, const int32_t *w,
-                                                  int32_t *err, unsigned long long *W)
+                                                  int32_t *err, unsigned long long *W,
+                                                  int32_t *wmax)
 {
     int e_off = 0, e_tgt = 0, e_w = 0;
+    int32_t m = 0;
     unsigned long long s = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -146,11 +148,14 @@ __global__ __launch_bounds__(256) void k_validate(int32_t n, int64_t nnz, const 
         if (t < 0 || t >= n) e_tgt = 1;
         if (x < 1) e_w = 1;
         s += (unsigned long long)(x > 0 ? x : 0);
+        m = max(m, x);
     }
     const int bits = e_off | (e_tgt << 1) | (e_w << 2);
     if (bits) atomicOr(err, bits);
     s = wave_sum_u64(s);
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(W, s);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(wmax, m);
 }
 
 __global__ void k_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,
@@ -920,10 +925,11 @@ void launch_iota(int32_t *p, int64_t n, hipStream_t s)
 
 
 void launch_validate(int32_t n, int64_t nnz, const int32_t *off, const int32_t *tgt,
-                     const int32_t *w, int32_t *err, unsigned long long *W, hipStream_t s)
+                     const int32_t *w, int32_t *err, unsigned long long *W, int32_t *wmax,
+                     hipStream_t s)
 {
     const int64_t m = nnz > n ? nnz : n;
-    k_validate<<<grid_for(m + 1, 256), 256, 0, s>>>(n, nnz, off, tgt, w, err, W);
+    k_validate<<<grid_for(m + 1, 256), 256, 0, s>>>(n, nnz, off, tgt, w, err, W, wmax);
 }
 
 void launch_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,

@@ -25,9 +25,11 @@ void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_iota(int32_t *p, int64_t n, hipStream_t s);
 
-// Validation of the input CSR; sets bits of *err and adds weights into *W.
+// Validation of the input CSR; sets bits of *err, adds weights into *W and
+// raises *wmax to the largest weight (both start at zero).
 void launch_validate(int32_t n, int64_t nnz, const int32_t *off, const int32_t *tgt,
-                     const int32_t *w, int32_t *err, unsigned long long *W, hipStream_t s);
+                     const int32_t *w, int32_t *err, unsigned long long *W, int32_t *wmax,
+                     hipStream_t s);
 
 // Per-level reset: C' = iota, size = 1, flagsA = 1, flagsB = 0, K = Sigma = 0.
 void launch_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,
@@ -300,8 +302,10 @@ void launch_aggregate(int bin, const AggArgs<C> &a, int log2s_max, hipStream_t s
 // Hub bin: one workgroup per AGG_PSLICE flattened entries of a community's
 // member rows folds and stages them and then sorts them into partitions; one
 // workgroup per partition folds it and appends its keys to the community's row.
+// wmax: the largest weight of the level when known (input weights), else 0; it
+// lets the first fold use 32-bit sums.
 template <class C>
 void launch_aggregate_hub(const AggArgs<C> &a, int32_t sort_slices, int32_t parts,
-                          int64_t *scratch, hipStream_t s);
+                          int64_t wmax, int64_t *scratch, hipStream_t s);
 
 }  // namespace lv

@@ -262,6 +262,7 @@ struct louvain_ctx {
     int32_t hub_slices;  // row slices of the current level's hubs
     int32_t hub_tslices; // partitions of the current level's hub rows
     int64_t W;
+    int32_t wmax;        // largest input weight
     bool wide;
     int32_t lds_max;     // LDS row limit of the bins (LDS_MAX_NARROW or LDS_MAX_WIDE)
     int32_t bin_maxlen[NBINS];
@@ -943,7 +944,8 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
         if (b < NBINS - 1)
             launch_aggregate<C>(b, g, block_log2s(cmax[b]), s);
         else
-            launch_aggregate_hub<C>(g, row_slices, table_slices, ctx->scratch, s);
+            launch_aggregate_hub<C>(g, row_slices, table_slices, l.buf < 0 ? ctx->wmax : 0,
+                                    ctx->scratch, s);
         CKL();
         TRY(prof_end(ctx, F_AGG0 + b, ev));
     }
@@ -1197,7 +1199,8 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->L = make_layout(n, nnz, 4, G);
     ctx->sc = (DevScalars *)(ctx->ws + ctx->L.scalars);
     launch_fill_bytes_zero(ctx->sc, sizeof(DevScalars), ctx->s);
-    launch_validate(n, nnz, offsets, targets, weights, &ctx->sc->err, &ctx->sc->W, ctx->s);
+    launch_validate(n, nnz, offsets, targets, weights, &ctx->sc->err, &ctx->sc->W, &ctx->sc->wmax,
+                    ctx->s);
     if (hipGetLastError() != hipSuccess) return fail(LOUVAIN_EHIP);
     if (hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->s) !=
             hipSuccess ||
@@ -1209,6 +1212,7 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     const unsigned long long W = ctx->hsc->W;
     if (W >= (1ull << 62)) return fail(LOUVAIN_EOVERFLOW);
     ctx->W = (int64_t)W;
+    ctx->wmax = ctx->hsc->wmax;
     ctx->wide = W >= (1ull << 31);
     ctx->lds_max = ctx->wide ? LDS_MAX_WIDE : LDS_MAX_NARROW;
     if (prm.hub_rows) ctx->lds_max = std::min(ctx->lds_max, prm.hub_rows);

@@ -148,6 +148,12 @@ def test_det_wide_totals():
     det_parity(heavy(graphgen.sbm(3000, 30, 0.03, 0.001, seed=42), 3), prune=False)
 
 
+def test_wide_totals_with_weights_below_2_19():
+    # W past 2^31 while every weight is below 2^19: the first aggregation folds the hub
+    # communities' windows of 4096 entries with 32-bit sums, which cannot overflow
+    det_parity(heavy(hub_graph(), 6, wmax=(1 << 19) - 1))
+
+
 def test_coloured_wide_totals():
     det_parity(heavy(hub_graph(), 4), coloured=True, seed=1)
 
