@@ -71,9 +71,12 @@ __host__ __device__ inline int hub_parts(int64_t d)
     return (int)(p < 1 ? 1 : (p > HUB_MAXP ? HUB_MAXP : p));
 }
 // Aggregation windows of hub communities: AGG_PSLICE = 2^AGG_PLOG2 flattened
-// member entries, folded in a table of twice as many slots.
+// member entries, each folded in an LDS table of AGG_FOLD_SLOTS slots.
 constexpr int AGG_PLOG2 = 12;
 constexpr int AGG_PSLICE = 1 << AGG_PLOG2;
+// Slots of a window's fold table: 11/8 of the window (at most 8/11 full), so
+// that three 256-thread workgroups with 32-bit sums fit in one CU's LDS.
+constexpr int AGG_FOLD_SLOTS = 11 * (AGG_PSLICE / 8);
 // Member entries per hash partition of a hub community: windows fold repeated
 // neighbours first, so partitions are cut for several times more entries than
 // an LDS partition table holds pairs.

@@ -36,6 +36,29 @@ __device__ inline void lds_add(int32_t *keys, ST *vals, int log2s, int32_t c, ST
     }
 }
 
+// lds_add over a table of any size ns (not only a power of two): the start slot
+// scales the hash into [0, ns).
+template <typename ST>
+__device__ inline void lds_add_n(int32_t *keys, ST *vals, uint32_t ns, int32_t c, ST w)
+{
+    uint32_t h = (uint32_t)(((uint64_t)hash32((uint32_t)c) * ns) >> 32);
+    for (;;) {
+        const int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == c) {
+            atomic_add_t<ST>(&vals[h], w);
+            return;
+        }
+        if (k < 0) {
+            const int32_t old = atomicCAS(&keys[h], -1, c);
+            if (old < 0 || old == c) {
+                atomic_add_t<ST>(&vals[h], w);
+                return;
+            }
+        }
+        h = h + 1 == ns ? 0 : h + 1;
+    }
+}
+
 // Position of the member owning flattened entry t: the first lane whose
 // inclusive prefix exceeds t.
 __device__ inline int owner_of(const int32_t *incl, int n, int t)
@@ -325,7 +348,7 @@ __device__ inline void agg_window(const AggArgs<C> &a, int nh, int k, int *idx, 
 }
 
 // Step 1: one workgroup per AGG_PSLICE flattened entries of a hub community
-// folds its window in an LDS table (dynamic shared memory of 2 * AGG_PSLICE
+// folds its window in an LDS table (dynamic shared memory of AGG_FOLD_SLOTS
 // slots), stages the window's distinct (community, weight) pairs at the
 // window's flattened offset (count in wcnt), and adds their count per
 // partition into pcount.  Folding first keeps a community's many entries
@@ -337,8 +360,7 @@ template <class C, class VT>
 __global__ __launch_bounds__(256) void k_agg_hub_count(AggArgs<C> a, int32_t nh)
 {
     typedef typename C::ST ST;
-    constexpr int LOG2S = AGG_PLOG2 + 1;
-    constexpr int S = 1 << LOG2S;
+    constexpr int S = AGG_FOLD_SLOTS;
     extern __shared__ __align__(16) unsigned char smem[];
     VT *vals = (VT *)smem;
     int32_t *keys = (int32_t *)(smem + (size_t)S * sizeof(VT));
@@ -355,7 +377,7 @@ __global__ __launch_bounds__(256) void k_agg_hub_count(AggArgs<C> a, int32_t nh)
     if (threadIdx.x == 0) s_n = 0;
     unsigned long long ne_ = 0, nm_ = 0;
     walk_window(a, W, mb, me, base, w0, w1, &nm_, [&](int t, int e) {
-        lds_add<VT>(keys, vals, LOG2S, a.Cp[a.tgt[e]], (VT)a.w[e]);
+        lds_add_n<VT>(keys, vals, (uint32_t)S, a.Cp[a.tgt[e]], (VT)a.w[e]);
         ++ne_;
     });
     int32_t *sk = a.hstage + base + w0;
@@ -536,7 +558,7 @@ void launch_aggregate(int bin, const AggArgs<C> &a, int log2s_max, hipStream_t s
 template <class C, class VT>
 void launch_agg_hub_count(const AggArgs<C> &a, int32_t sort_slices, hipStream_t s)
 {
-    const size_t bytes = ((size_t)2 << AGG_PLOG2) * (sizeof(VT) + 4);
+    const size_t bytes = (size_t)AGG_FOLD_SLOTS * (sizeof(VT) + 4);
     if (bytes > 32768) {
         // raise the dynamic-LDS limit of this kernel to what the launch asks for; a
         // failure shows up as a launch error at the caller's check
