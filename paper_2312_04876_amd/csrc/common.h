@@ -18,16 +18,22 @@ typedef __int128 i128;
 
 // ---------------------------------------------------------------------------
 // Type configurations: WT = stored weight of the current level, ST = K',
-// Sigma' and table accumulator, SC = score arithmetic.
-template <typename WT_, typename ST_, typename SC_>
+// Sigma' and table accumulator, SC = score arithmetic, VT = value of the LDS
+// tables of local moving (sums of one row's weights per community).
+template <typename WT_, typename ST_, typename SC_, typename VT_ = ST_>
 struct Cfg {
     typedef WT_ WT;
     typedef ST_ ST;
     typedef SC_ SC;
+    typedef VT_ VT;
 };
 typedef Cfg<int32_t, int32_t, int64_t> CfgNarrow;  // W < 2^31, every level
 typedef Cfg<int32_t, int64_t, i128> CfgWideIn;     // W >= 2^31, input level (int32 weights)
 typedef Cfg<int64_t, int64_t, i128> CfgWide;       // W >= 2^31, aggregated levels
+// W >= 2^31, input level, longest row times largest weight below 2^31: no
+// row's sum can overflow 32 bits, so local moving keeps 32-bit LDS tables
+// (half the LDS of CfgWideIn, more workgroups per CU)
+typedef Cfg<int32_t, int64_t, i128, int32_t> CfgWideIn32;
 
 // ---------------------------------------------------------------------------
 // Degree bins.  A vertex (or, in aggregation, a community with its total
@@ -138,6 +144,8 @@ struct DevScalars {
     // --- fields above are cleared at the start of every local-moving phase ---
     int32_t err;            // validation: bits 0-2 offsets/targets/weights, 3 batch, 4 labels
     int32_t wmax;           // validation: largest input weight
+    int32_t dmax;           // validation: longest input row
+    int32_t pad1;
     unsigned long long scan_total;
     unsigned long long hub_slices;   // row slices of the hub bin (sum over hubs)
     unsigned long long hub_tslices;  // table slices of the hub bin

@@ -277,7 +277,8 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
     constexpr int PLOG2 = 4 * NG * FL <= 256 ? 8 : (4 * NG * FL <= 512 ? 9 : 10);  // >= 4 slots/vertex
     constexpr int PS = FAST ? 1 << PLOG2 : 1;
     static_assert(!FAST || PS >= 4 * NG * FL, "pending table too small");
-    __shared__ ST s_vals[NG * SP];
+    typedef typename C::VT VT;
+    __shared__ VT s_vals[NG * SP];
     __shared__ int32_t s_keys[NG * SP];
     __shared__ int32_t p_keys[PS];
     __shared__ ST p_sig[PS];
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / G, gl = lane % G;
     int32_t *keys = s_keys + (wave * GPW + grp) * SP;
-    ST *vals = s_vals + (wave * GPW + grp) * SP;
+    VT *vals = s_vals + (wave * GPW + grp) * SP;
     for (int q = gl; q < S; q += G) {
         keys[q] = -1;
         vals[q] = 0;
@@ -338,14 +339,14 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             own[k] = false;
             if (c[k] >= 0) {
                 ++nonself;
-                slot[k] = lds_insert_slot<ST>(keys, vals, LOG2S, c[k], w[k], &own[k]);
+                slot[k] = lds_insert_slot<VT>(keys, vals, LOG2S, c[k], (VT)w[k], &own[k]);
                 nk += own[k] ? 1 : 0;
             }
         }
         wave_sync();
         ST x[E], sg[E];
 #pragma unroll
-        for (int k = 0; k < E; ++k) x[k] = own[k] ? vals[slot[k]] : (ST)0;
+        for (int k = 0; k < E; ++k) x[k] = own[k] ? (ST)vals[slot[k]] : (ST)0;
 #pragma unroll
         for (int k = 0; k < E; ++k) sg[k] = (own[k] && c[k] != dc) ? a.Sig[c[k]] : (ST)0;
         SC best = score_min<SC>();
@@ -469,9 +470,10 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
     constexpr int NW = BT / 64;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ BlockRed<SC, ST, NW> r;
+    typedef typename C::VT VT;
     const int S_max = 1 << log2s_max;
-    ST *s_vals = (ST *)smem;
-    int32_t *s_keys = (int32_t *)(smem + (size_t)S_max * sizeof(ST));
+    VT *s_vals = (VT *)smem;
+    int32_t *s_keys = (int32_t *)(smem + (size_t)S_max * sizeof(VT));
     if (*a.done) return;
     const int count = *a.count;
     if (count == 0) return;
@@ -505,7 +507,7 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
                 ne += j[k] >= 0 ? 1 : 0;
                 if (c[k] >= 0) {
                     ++nonself;
-                    nk += lds_insert<ST>(s_keys, s_vals, log2s, c[k], w[k]);
+                    nk += lds_insert<VT>(s_keys, s_vals, log2s, c[k], (VT)w[k]);
                 }
             }
         }
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
             for (int q = 0; q < 4; ++q) {
                 const int s = s0 + q * BT;
                 kk[q] = s < (1 << log2s) ? s_keys[s] : -1;
-                xx[q] = kk[q] >= 0 ? s_vals[s] : (ST)0;
+                xx[q] = kk[q] >= 0 ? (ST)s_vals[s] : (ST)0;
                 if (kk[q] >= 0) {
                     s_keys[s] = -1;
                     s_vals[s] = 0;
@@ -666,11 +668,12 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
 {
     typedef typename C::ST ST;
     typedef typename C::SC SC;
+    typedef typename C::VT VT;
     constexpr int LOG2S = hub_plog2<ST>();
     constexpr int S = 1 << LOG2S;
     extern __shared__ __align__(16) unsigned char smem[];
-    ST *vals = (ST *)smem;
-    int32_t *keys = (int32_t *)(smem + (size_t)S * sizeof(ST));
+    VT *vals = (VT *)smem;
+    int32_t *keys = (int32_t *)(smem + (size_t)S * sizeof(VT));
     __shared__ BlockRed<SC, ST, 4> r;
     __shared__ uint64_t st_lo[40], st_hi[40];
     __shared__ int s_sp, s_cnt, s_over;
@@ -719,7 +722,7 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
                 const uint64_t x = hash32(mix32((uint32_t)c) ^ 0x5bd1e995u);
                 if (x < lo || x >= hi) continue;
             }
-            if (!lds_insert_capped<ST>(keys, vals, lg, c, a.pw[pb + i], &s_cnt, capu)) s_over = 1;
+            if (!lds_insert_capped<VT>(keys, vals, lg, c, (VT)a.pw[pb + i], &s_cnt, capu)) s_over = 1;
         }
         __syncthreads();
         if (s_over) {
@@ -746,7 +749,7 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
             for (int q = 0; q < 4; ++q) {
                 const int s = s0 + q * 256;
                 kk[q] = s < Su ? keys[s] : -1;
-                xx[q] = kk[q] >= 0 ? vals[s] : (ST)0;
+                xx[q] = kk[q] >= 0 ? (ST)vals[s] : (ST)0;
                 if (kk[q] >= 0) {
                     keys[s] = -1;
                     vals[s] = 0;
@@ -835,7 +838,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
 template <class C, int BT, bool FAST>
 void launch_block(const MoveArgs<C> &a, int grid, int log2s_max, hipStream_t s)
 {
-    const size_t bytes = ((size_t)1 << log2s_max) * (sizeof(typename C::ST) + 4);
+    const size_t bytes = ((size_t)1 << log2s_max) * (sizeof(typename C::VT) + 4);
     if (bytes > 65536) {
         // raise the dynamic-LDS limit of this kernel to what the launch asks for; a
         // failure shows up as a launch error at the caller's check
@@ -884,6 +887,8 @@ template void launch_move<CfgNarrow>(int, bool, const MoveArgs<CfgNarrow> &, int
 template void launch_move<CfgWideIn>(int, bool, const MoveArgs<CfgWideIn> &, int, int,
                                      hipStream_t);
 template void launch_move<CfgWide>(int, bool, const MoveArgs<CfgWide> &, int, int, hipStream_t);
+template void launch_move<CfgWideIn32>(int, bool, const MoveArgs<CfgWideIn32> &, int, int,
+                                       hipStream_t);
 
 template <class C>
 void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int32_t parts,
@@ -903,7 +908,7 @@ void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int3
     k_hub_count<C><<<sort_slices, 256, 0, s>>>(a);
     launch_exclusive_scan<int32_t, int32_t>(a.pcount + pb, a.poff + pb, parts, scratch, nullptr, s);
     k_hub_fill<C><<<sort_slices, 256, 0, s>>>(a);
-    const size_t bytes = ((size_t)1 << hub_plog2<ST>()) * (sizeof(ST) + 4);
+    const size_t bytes = ((size_t)1 << hub_plog2<ST>()) * (sizeof(typename C::VT) + 4);
     if (bytes > 65536) {
         // raise the dynamic-LDS limit of this kernel to what the launch asks for; a
         // failure shows up as a launch error at the caller's check
@@ -923,5 +928,7 @@ template void launch_move_hubs<CfgWideIn>(bool, const MoveArgs<CfgWideIn> &, int
                                           int, int64_t *, hipStream_t);
 template void launch_move_hubs<CfgWide>(bool, const MoveArgs<CfgWide> &, int32_t, int32_t, int,
                                         int64_t *, hipStream_t);
+template void launch_move_hubs<CfgWideIn32>(bool, const MoveArgs<CfgWideIn32> &, int32_t, int32_t,
+                                            int, int64_t *, hipStream_t);
 
 }  // namespace lv

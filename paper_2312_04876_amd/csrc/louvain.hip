@@ -264,6 +264,7 @@ struct louvain_ctx {
     int64_t W;
     int32_t wmax;        // largest input weight
     bool wide;
+    bool rows32;         // every input row's weight sum is below 2^31
     int32_t lds_max;     // LDS row limit of the bins (LDS_MAX_NARROW or LDS_MAX_WIDE)
     int32_t bin_maxlen[NBINS];
     int state;
@@ -1047,7 +1048,8 @@ int dispatch_move(louvain_ctx *ctx)
 int do_move(louvain_ctx *ctx)
 {
     if (!ctx->wide) return move_phase<CfgNarrow>(ctx);
-    if (ctx->lev.buf < 0) return move_phase<CfgWideIn>(ctx);
+    if (ctx->lev.buf < 0)
+        return ctx->rows32 ? move_phase<CfgWideIn32>(ctx) : move_phase<CfgWideIn>(ctx);
     return move_phase<CfgWide>(ctx);
 }
 
@@ -1200,7 +1202,7 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->sc = (DevScalars *)(ctx->ws + ctx->L.scalars);
     launch_fill_bytes_zero(ctx->sc, sizeof(DevScalars), ctx->s);
     launch_validate(n, nnz, offsets, targets, weights, &ctx->sc->err, &ctx->sc->W, &ctx->sc->wmax,
-                    ctx->s);
+                    &ctx->sc->dmax, ctx->s);
     if (hipGetLastError() != hipSuccess) return fail(LOUVAIN_EHIP);
     if (hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->s) !=
             hipSuccess ||
@@ -1214,6 +1216,7 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->W = (int64_t)W;
     ctx->wmax = ctx->hsc->wmax;
     ctx->wide = W >= (1ull << 31);
+    ctx->rows32 = (int64_t)ctx->hsc->dmax * ctx->hsc->wmax < ((int64_t)1 << 31);
     ctx->lds_max = ctx->wide ? LDS_MAX_WIDE : LDS_MAX_NARROW;
     if (prm.hub_rows) ctx->lds_max = std::min(ctx->lds_max, prm.hub_rows);
     ctx->L = make_layout(n, nnz, ctx->wide ? 8 : 4, G);

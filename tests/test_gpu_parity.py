@@ -154,6 +154,23 @@ def test_wide_totals_with_weights_below_2_19():
     det_parity(heavy(hub_graph(), 6, wmax=(1 << 19) - 1))
 
 
+def test_wide_totals_with_rows_below_2_31():
+    # W past 2^31 while the longest row times the largest weight stays below 2^31: local
+    # moving on the input level keeps 32-bit LDS tables (every bin, hubs included)
+    import paper_2312_04876_amd as P
+    csr = heavy(hub_graph(), 7, wmax=1 << 16)
+    assert int(np.diff(csr.offsets).max()) * int(csr.weights.max()) < 1 << 31
+    det_parity(csr)
+    det_parity(csr, coloured=True, seed=2)
+    g = _og(csr)
+    memb, q, _ = P.louvain(*to_device(csr), mode="fast")
+    memb = memb.cpu().numpy()
+    assert is_valid_partition(memb)
+    assert q == oracle.modularity(g, memb)
+    _, q_seq, _ = oracle.louvain(g, oracle.Params(mode="seq"))
+    assert abs(q - q_seq) <= 0.01
+
+
 def test_coloured_wide_totals():
     det_parity(heavy(hub_graph(), 4), coloured=True, seed=1)
 
