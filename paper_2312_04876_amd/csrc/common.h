@@ -30,9 +30,9 @@ struct Cfg {
 typedef Cfg<int32_t, int32_t, int64_t> CfgNarrow;  // W < 2^31, every level
 typedef Cfg<int32_t, int64_t, i128> CfgWideIn;     // W >= 2^31, input level (int32 weights)
 typedef Cfg<int64_t, int64_t, i128> CfgWide;       // W >= 2^31, aggregated levels
-// W >= 2^31, input level, longest row times largest weight below 2^31: no
-// row's sum can overflow 32 bits, so local moving keeps 32-bit LDS tables
-// (half the LDS of CfgWideIn, more workgroups per CU)
+// W >= 2^31, input level, every K' below 2^31: no sum of one row's weights
+// can overflow 32 bits, so local moving keeps 32-bit LDS tables (half the LDS
+// of CfgWideIn, more workgroups per CU)
 typedef Cfg<int32_t, int64_t, i128, int32_t> CfgWideIn32;
 
 // ---------------------------------------------------------------------------
@@ -141,11 +141,10 @@ struct DevScalars {
     int32_t bin_maxlen[8];  // longest row per bin (binning step)
     int32_t mv_count;       // deferred moves of the current round (deterministic mode)
     int32_t running;        // batches: graphs still moving after this iteration (then reset)
+    unsigned long long kmax;  // wide input level: largest K' (level setup)
     // --- fields above are cleared at the start of every local-moving phase ---
     int32_t err;            // validation: bits 0-2 offsets/targets/weights, 3 batch, 4 labels
     int32_t wmax;           // validation: largest input weight
-    int32_t dmax;           // validation: longest input row
-    int32_t pad1;
     unsigned long long scan_total;
     unsigned long long hub_slices;   // row slices of the hub bin (sum over hubs)
     unsigned long long hub_tslices;  // table slices of the hub bin

@@ -132,18 +132,16 @@ __global__ void k_iota(int32_t *p, int64_t n)
 __global__ __launch_bounds__(256) void k_validate(int32_t n, int64_t nnz, const int32_t *off,
                                                   const int32_t *tgt, const int32_t *w,
                                                   int32_t *err, unsigned long long *W,
-                                                  int32_t *wmax, int32_t *dmax)
+                                                  int32_t *wmax)
 {
     int e_off = 0, e_tgt = 0, e_w = 0;
-    int32_t m = 0, dm = 0;
+    int32_t m = 0;
     unsigned long long s = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gid == 0 && (off[0] != 0 || (int64_t)off[n] != nnz)) e_off = 1;
-    for (int64_t i = gid; i < n; i += stride) {
+    for (int64_t i = gid; i < n; i += stride)
         if (off[i] > off[i + 1]) e_off = 1;
-        dm = max(dm, off[i + 1] - off[i]);
-    }
     for (int64_t e = gid; e < nnz; e += stride) {
         const int32_t t = tgt[e];
         const int32_t x = w[e];
@@ -156,12 +154,24 @@ __global__ __launch_bounds__(256) void k_validate(int32_t n, int64_t nnz, const 
     if (bits) atomicOr(err, bits);
     s = wave_sum_u64(s);
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(W, s);
-    for (int o = 32; o > 0; o >>= 1) {
-        m = max(m, __shfl_xor(m, o, 64));
-        dm = max(dm, __shfl_xor(dm, o, 64));
-    }
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(wmax, m);
-    if ((threadIdx.x & 63) == 0 && dm > 0) atomicMax(dmax, dm);
+}
+
+__global__ __launch_bounds__(256) void k_max_u64(const int64_t *x, int32_t n,
+                                                 unsigned long long *out)
+{
+    unsigned long long m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long v = (unsigned long long)x[i];
+        m = v > m ? v : m;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long v = (unsigned long long)shfl_xor_t<int64_t>((int64_t)m, o);
+        m = v > m ? v : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
 }
 
 __global__ void k_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,
@@ -932,10 +942,15 @@ void launch_iota(int32_t *p, int64_t n, hipStream_t s)
 
 void launch_validate(int32_t n, int64_t nnz, const int32_t *off, const int32_t *tgt,
                      const int32_t *w, int32_t *err, unsigned long long *W, int32_t *wmax,
-                     int32_t *dmax, hipStream_t s)
+                     hipStream_t s)
 {
     const int64_t m = nnz > n ? nnz : n;
-    k_validate<<<grid_for(m + 1, 256), 256, 0, s>>>(n, nnz, off, tgt, w, err, W, wmax, dmax);
+    k_validate<<<grid_for(m + 1, 256), 256, 0, s>>>(n, nnz, off, tgt, w, err, W, wmax);
+}
+
+void launch_max_u64(const int64_t *x, int32_t n, unsigned long long *out, hipStream_t s)
+{
+    if (n > 0) k_max_u64<<<grid_for(n, 256, 2048), 256, 0, s>>>(x, n, out);
 }
 
 void launch_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,

@@ -26,11 +26,13 @@ void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_iota(int32_t *p, int64_t n, hipStream_t s);
 
 // Validation of the input CSR; sets bits of *err, adds weights into *W and
-// raises *wmax to the largest weight and *dmax to the longest row (all start
-// at zero).
+// raises *wmax to the largest weight (both start at zero).
 void launch_validate(int32_t n, int64_t nnz, const int32_t *off, const int32_t *tgt,
                      const int32_t *w, int32_t *err, unsigned long long *W, int32_t *wmax,
-                     int32_t *dmax, hipStream_t s);
+                     hipStream_t s);
+
+// *out = max(*out, max of x[0..n)) for non-negative x.
+void launch_max_u64(const int64_t *x, int32_t n, unsigned long long *out, hipStream_t s);
 
 // Per-level reset: C' = iota, size = 1, flagsA = 1, flagsB = 0, K = Sigma = 0.
 void launch_init_vertices(int32_t n, int32_t *Cp, int32_t *size, uint8_t *fa, uint8_t *fb,

@@ -264,7 +264,7 @@ struct louvain_ctx {
     int64_t W;
     int32_t wmax;        // largest input weight
     bool wide;
-    bool rows32;         // every input row's weight sum is below 2^31
+    unsigned long long kmax_in;  // largest K' of the input level (wide graphs, after its setup)
     int32_t lds_max;     // LDS row limit of the bins (LDS_MAX_NARROW or LDS_MAX_WIDE)
     int32_t bin_maxlen[NBINS];
     int state;
@@ -470,11 +470,21 @@ int setup_level(louvain_ctx *ctx)
                                            ctx->Cp, (typename C::ST *)ctx->Sig, ctx->size, s);
         CKL();
     }
+    // the input level of a wide graph: its largest K' decides the width of the
+    // local-moving tables
+    const bool want_kmax = ctx->wide && l.buf < 0;
+    if (want_kmax) {
+        launch_max_u64((const int64_t *)ctx->K, l.n, &ctx->sc->kmax, s);
+        CKL();
+    }
     TRY(prof_end(ctx, F_SETUP, ev));
-    if (hubs > 0) {
+    if (hubs > 0 || want_kmax) {
         TRY(read_scalars(ctx));
-        ctx->hub_slices = (int32_t)ctx->hsc->hub_slices;
-        ctx->hub_tslices = (int32_t)ctx->hsc->hub_tslices;
+        if (hubs > 0) {
+            ctx->hub_slices = (int32_t)ctx->hsc->hub_slices;
+            ctx->hub_tslices = (int32_t)ctx->hsc->hub_tslices;
+        }
+        if (want_kmax) ctx->kmax_in = ctx->hsc->kmax;
     }
     return LOUVAIN_OK;
 }
@@ -619,12 +629,12 @@ int colour_level(louvain_ctx *ctx)
 
 // ---------------------------------------------------------------- local moving (Alg. 2)
 template <class C>
-int move_phase(louvain_ctx *ctx)
+int move_phase(louvain_ctx *ctx, bool level_ready = false)
 {
     typedef typename C::ST ST;
     hipStream_t s = ctx->s;
     const LevelH &l = ctx->lev;
-    TRY(setup_level<C>(ctx));
+    if (!level_ready) TRY(setup_level<C>(ctx));
     const bool fast = ctx->p.mode == LOUVAIN_FAST;
     const bool coloured = ctx->p.mode == LOUVAIN_COLOURED;
     if (coloured) TRY(colour_level<C>(ctx));
@@ -1048,8 +1058,13 @@ int dispatch_move(louvain_ctx *ctx)
 int do_move(louvain_ctx *ctx)
 {
     if (!ctx->wide) return move_phase<CfgNarrow>(ctx);
-    if (ctx->lev.buf < 0)
-        return ctx->rows32 ? move_phase<CfgWideIn32>(ctx) : move_phase<CfgWideIn>(ctx);
+    if (ctx->lev.buf < 0) {
+        // set the level up first: its largest K' bounds every sum of one row's
+        // weights, so below 2^31 the LDS tables can hold 32-bit sums
+        TRY(setup_level<CfgWideIn>(ctx));
+        if (ctx->kmax_in < (1ull << 31)) return move_phase<CfgWideIn32>(ctx, true);
+        return move_phase<CfgWideIn>(ctx, true);
+    }
     return move_phase<CfgWide>(ctx);
 }
 
@@ -1202,7 +1217,7 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->sc = (DevScalars *)(ctx->ws + ctx->L.scalars);
     launch_fill_bytes_zero(ctx->sc, sizeof(DevScalars), ctx->s);
     launch_validate(n, nnz, offsets, targets, weights, &ctx->sc->err, &ctx->sc->W, &ctx->sc->wmax,
-                    &ctx->sc->dmax, ctx->s);
+                    ctx->s);
     if (hipGetLastError() != hipSuccess) return fail(LOUVAIN_EHIP);
     if (hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->s) !=
             hipSuccess ||
@@ -1216,7 +1231,6 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->W = (int64_t)W;
     ctx->wmax = ctx->hsc->wmax;
     ctx->wide = W >= (1ull << 31);
-    ctx->rows32 = (int64_t)ctx->hsc->dmax * ctx->hsc->wmax < ((int64_t)1 << 31);
     ctx->lds_max = ctx->wide ? LDS_MAX_WIDE : LDS_MAX_NARROW;
     if (prm.hub_rows) ctx->lds_max = std::min(ctx->lds_max, prm.hub_rows);
     ctx->L = make_layout(n, nnz, ctx->wide ? 8 : 4, G);

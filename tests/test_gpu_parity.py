@@ -155,11 +155,12 @@ def test_wide_totals_with_weights_below_2_19():
 
 
 def test_wide_totals_with_rows_below_2_31():
-    # W past 2^31 while the longest row times the largest weight stays below 2^31: local
-    # moving on the input level keeps 32-bit LDS tables (every bin, hubs included)
+    # W past 2^31 while every row sum K' stays below 2^31: local moving on the input level
+    # keeps 32-bit LDS tables (every bin, hubs included)
     import paper_2312_04876_amd as P
     csr = heavy(hub_graph(), 7, wmax=1 << 16)
-    assert int(np.diff(csr.offsets).max()) * int(csr.weights.max()) < 1 << 31
+    src = np.repeat(np.arange(csr.n), np.diff(csr.offsets))
+    assert np.bincount(src, weights=csr.weights.astype(np.float64)).max() < 2.0 ** 31
     det_parity(csr)
     det_parity(csr, coloured=True, seed=2)
     g = _og(csr)
