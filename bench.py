@@ -88,9 +88,9 @@ FAMILY_KERNELS = {
     "move_bin4_block": [r"k_move_block<[^>]*>, 256,"],
     "move_bin5_bigblock": [r"k_move_block<[^>]*>, 512,"],
     "move_bin6_hub": [r"k_move_hub<", r"k_hub_count<", r"k_hub_fill<", r"k_hub_part<"],
-    "agg_bin0_8lanes": [r"k_agg_wave<[^>]*>, 8, 4>"],
-    "agg_bin1_32lanes": [r"k_agg_wave<[^>]*>, 32, 6>"],
-    "agg_bin2_wave": [r"k_agg_wave<[^>]*>, 64, 8>"],
+    "agg_bin0_4lanes": [r"k_agg_wave<[^>]*>, 4, 4>"],
+    "agg_bin1_4lanes": [r"k_agg_wave<[^>]*>, 4, 6>"],
+    "agg_bin2_8lanes": [r"k_agg_wave<[^>]*>, (8|16), 8>"],  # 16 lanes with 8-byte sums
     "agg_bin3_wave": [r"k_agg_wave<[^>]*>, 64, 10>"],
     "agg_bin6_hub": [r"k_agg_hub_part<", r"k_agg_hub_count<", r"k_agg_hub_fill<"],
 }

@@ -533,9 +533,17 @@ void launch_aggregate(int bin, const AggArgs<C> &a, int log2s_max, hipStream_t s
 {
     if (a.count <= 0) return;
     switch (bin) {
-    case 0: k_agg_wave<C, 8, 4><<<agg_grid(a.count, 32), 256, 0, s>>>(a); break;
-    case 1: k_agg_wave<C, 32, 6><<<agg_grid(a.count, 8), 256, 0, s>>>(a); break;
-    case 2: k_agg_wave<C, 64, 8><<<agg_grid(a.count, 4), 256, 0, s>>>(a); break;
+    // few lanes per community keep many small communities in flight (measured
+    // against 8, 32 and 64 lanes for bins 0-2); bin 2 with 8-byte sums takes 16
+    // lanes so that its tables leave room for more than one workgroup per CU
+    case 0: k_agg_wave<C, 4, 4><<<agg_grid(a.count, 64), 256, 0, s>>>(a); break;
+    case 1: k_agg_wave<C, 4, 6><<<agg_grid(a.count, 64), 256, 0, s>>>(a); break;
+    case 2:
+        if (sizeof(typename C::ST) > 4)
+            k_agg_wave<C, 16, 8><<<agg_grid(a.count, 16), 256, 0, s>>>(a);
+        else
+            k_agg_wave<C, 8, 8><<<agg_grid(a.count, 32), 256, 0, s>>>(a);
+        break;
     case 3: k_agg_wave<C, 64, 10><<<agg_grid(a.count, 4), 256, 0, s>>>(a); break;
     case 4:
     case 5: {

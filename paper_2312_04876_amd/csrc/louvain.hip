@@ -159,8 +159,8 @@ enum Fam {
 };
 const char *FAM_NAMES[F_COUNT] = {
     "move_bin0_1lane", "move_bin1_4lanes", "move_bin2_16lanes", "move_bin3_wave",
-    "move_bin4_block", "move_bin5_bigblock", "move_bin6_hub", "agg_bin0_8lanes",
-    "agg_bin1_32lanes", "agg_bin2_wave", "agg_bin3_wave", "agg_bin4_block",
+    "move_bin4_block", "move_bin5_bigblock", "move_bin6_hub", "agg_bin0_4lanes",
+    "agg_bin1_4lanes", "agg_bin2_8lanes", "agg_bin3_wave", "agg_bin4_block",
     "agg_bin5_bigblock", "agg_bin6_hub", "compact", "apply", "iteration_end", "level_setup",
     "aggregate_prep", "final", "colour"};
 static_assert(F_COUNT == 2 * NBINS + 7, "family names");
