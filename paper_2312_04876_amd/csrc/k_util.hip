@@ -464,6 +464,7 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a)
             pos_of[r] = (int32_t)p;
             const int v = a.binorder[p];
             bool act = a.prune ? (a.flags[v] != 0) : true;
+            if (a.hubs_only && p < a.bins.start[NBINS - 1]) act = false;
             int lv = v;  // index within its graph (a batch numbers each graph from 0)
             if (a.bt.gid) {
                 const int g = a.bt.gid[v];
@@ -508,6 +509,57 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a)
                                 wcnt[3][threadIdx.x];
         __syncthreads();
     }
+}
+
+// Colour-ordered mode: every round's rows but the hubs in one pass (see
+// launch_compact_keys).  Ranks come from one atomic per distinct key of a
+// wavefront; keys are sorted, so a wavefront rarely holds more than two.
+__global__ __launch_bounds__(256) void k_compact_keys(CompactArgs a, const int32_t *koff,
+                                                      int32_t nkeys, int32_t *kact, int32_t *klist,
+                                                      unsigned long long *processed)
+{
+    if (*a.done) return;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = lanes_below();
+    const int32_t hub_start = a.bins.start[NBINS - 1];
+    unsigned long long nact = 0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < a.nb; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        bool act = false;
+        int k = 0, v = 0;
+        if (i < a.nb) {
+            const int p = a.order[i];
+            if (p < hub_start) {  // hub rows: the round's own compaction
+                v = a.binorder[p];
+                act = a.prune ? (a.flags[v] != 0) : true;
+                if (a.bt.gid && a.bt.gst[a.bt.gid[v]]) act = false;
+                if (act) {
+                    if (a.prune) a.flags[v] = 0;
+                    k = owner_slice(koff, nkeys, (int)i);
+                }
+            }
+        }
+        int rank = 0;
+        unsigned long long pending = __ballot(act);
+        while (pending) {  // uniform over the wavefront
+            const int leader = __ffsll((long long)pending) - 1;
+            const int k0 = __shfl(k, leader, 64);
+            const bool mine = act && k == k0;
+            const unsigned long long m = __ballot(mine);
+            int b0 = 0;
+            if (lane == leader) b0 = atomicAdd(&kact[k0], __popcll(m));
+            b0 = __shfl(b0, leader, 64);
+            if (mine) rank = b0 + __popcll(m & below);
+            pending &= ~m;
+        }
+        if (act) {
+            klist[koff[k] + rank] = v;
+            ++nact;
+        }
+    }
+    nact = wave_sum_u64(nact);
+    if (lane == 0 && nact) atomicAdd(processed, nact);
 }
 
 // Slot of community c in the apply kernel's LDS table (inserted if absent).
@@ -1046,6 +1098,14 @@ void launch_compact(const CompactArgs &a, hipStream_t s)
 {
     const int32_t len = a.order ? a.q1 - a.q0 : a.nb;
     if (len > 0) k_compact<<<bin_chunks(len), 256, 0, s>>>(a);
+}
+
+void launch_compact_keys(const CompactArgs &a, const int32_t *koff, int32_t nkeys, int32_t *kact,
+                         int32_t *klist, unsigned long long *processed, hipStream_t s)
+{
+    if (a.nb > 0 && nkeys > 0)
+        k_compact_keys<<<grid_for(a.nb, 256, 4096), 256, 0, s>>>(a, koff, nkeys, kact, klist,
+                                                                 processed);
 }
 
 template <typename ST>

@@ -154,8 +154,16 @@ struct CompactArgs {
     uint8_t *hub_act;   // per hub (position - bins.start[NBINS-1]): queued this round
     const int32_t *done;
     BatchArgs bt;       // batches: skip graphs that converged or stopped; rounds by local index
+    int32_t hubs_only;  // take only hub rows (the other rows were taken by launch_compact_keys)
 };
 void launch_compact(const CompactArgs &a, hipStream_t s);
+
+// Colour-ordered mode: the rows of every round at once, hub rows excepted.  Position
+// i of a.order (keys sorted (colour, bin); key k owns [koff[k], koff[k + 1])) goes,
+// when active, to klist[koff[k] + rank] with rank from kact[k] (zero on entry); the
+// order within a key is free.  Adds the rows taken to *processed.
+void launch_compact_keys(const CompactArgs &a, const int32_t *koff, int32_t nkeys, int32_t *kact,
+                         int32_t *klist, unsigned long long *processed, hipStream_t s);
 
 // Best candidate of one partition of a hub row.
 template <class C>

@@ -690,6 +690,33 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
         uint8_t *cur = (it & 1) ? ctx->fb : ctx->fa;
         uint8_t *nxt = (it & 1) ? ctx->fa : ctx->fb;
         a.flags_next = nxt;
+        if (coloured && ctx->ncol > 0) {
+            // every round's rows but the hubs, compacted once: the active set of an
+            // iteration is fixed when it starts (movers flag the next one)
+            const int32_t nkeys = ctx->ncol * NBINS;
+            CompactArgs ka;
+            memset(&ka, 0, sizeof(ka));
+            ka.binorder = ctx->binorder;
+            ka.nb = ctx->nb;
+            ka.bins = ctx->bins;
+            ka.flags = cur;
+            ka.prune = ctx->p.prune;
+            ka.pass = ctx->pass;
+            ka.it = it;
+            ka.seed = ctx->p.seed;
+            ka.order = ctx->corder;
+            ka.q0 = 0;
+            ka.q1 = ctx->nb;
+            ka.hub_act = ctx->hub_act;
+            ka.done = &ctx->sc->done;
+            ka.bt = a.bt;
+            hipEvent_t ev;
+            TRY(prof_begin(ctx, &ev));
+            launch_fill_i32(ctx->kcnt, 0, nkeys, s);
+            launch_compact_keys(ka, ctx->koff, nkeys, ctx->kcnt, ctx->front, &ctx->sc->processed[it], s);
+            CKL();
+            TRY(prof_end(ctx, F_COMPACT, ev));
+        }
         for (int r = 0; r < rounds; ++r) {
             int rgrid[NBINS];
             int32_t cap = ctx->nb;
@@ -728,15 +755,26 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
             ca.hub_act = ctx->hub_act;
             ca.done = &ctx->sc->done;
             ca.bt = a.bt;
+            ca.hubs_only = coloured ? 1 : 0;  // the other rows: launch_compact_keys above
             hipEvent_t ev;
-            TRY(prof_begin(ctx, &ev));
-            launch_compact(ca, s);
-            CKL();
-            TRY(prof_end(ctx, F_COMPACT, ev));
+            if (!coloured || hub1 > hub0) {
+                TRY(prof_begin(ctx, &ev));
+                launch_compact(ca, s);
+                CKL();
+                TRY(prof_end(ctx, F_COMPACT, ev));
+            }
             for (int b = 0; b < NBINS; ++b) {
                 if (rgrid[b] <= 0) continue;
-                a.list_begin = ctx->bins.start[b];
-                a.count = &ctx->sc->bin_count[b];
+                if (coloured && b < NBINS - 1) {
+                    // round r's rows of bin b, from the per-iteration keyed compaction
+                    a.worklist = ctx->front;
+                    a.list_begin = ctx->koff_h[(size_t)r * NBINS + b];
+                    a.count = ctx->kcnt + (size_t)r * NBINS + b;
+                } else {
+                    a.worklist = ctx->worklist;
+                    a.list_begin = ctx->bins.start[b];
+                    a.count = &ctx->sc->bin_count[b];
+                }
                 a.bin = b;
                 TRY(prof_begin(ctx, &ev));
                 if (b < NBINS - 1) {
