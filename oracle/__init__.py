@@ -21,11 +21,13 @@ function cites the passage of the paper it follows:
 Parity pins live in ``tests/test_oracle_*.py``.  The synchronous iteration
 (``mode="sync"``) is not in the paper; its semantics (hashed rounds, each
 deciding against the state at the start of the round, min-label rule for
-singleton-to-singleton moves) are pinned only by hand-worked cases and
-invariants: parity unpinned beyond those.  The colour-ordered iteration
+singleton-to-singleton moves) are pinned by hand-worked cases, invariants and a
+brute-force recomputation of whole iterations on small graphs
+(``tests/test_oracle_sync_bruteforce.py``).  The colour-ordered iteration
 (``mode="colour"``, one synchronous round per colour class of a greedy colouring
 in hashed priority order) is pinned by the colouring's defining properties, a
-hand-worked case and its reduction to the sequential sweep on a clique.
+hand-worked case, its reduction to the sequential sweep on a clique and the same
+brute force with colour classes as rounds.
 """
 from __future__ import annotations
 

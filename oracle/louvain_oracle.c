@@ -51,11 +51,13 @@
  * parity pins: modularity, the move gain, the sequential sweep, renumbering,
  * the community-vertex CSR, aggregation and the whole pass loop are each
  * checked against independent definitions in the CPU test-suite; the
- * synchronous iteration is pinned by hand-worked cases and invariants only
- * (parity unpinned beyond them); the colouring is pinned by its defining
- * properties (proper, greedy-minimal in priority order) and the colour-ordered
- * iteration by its reduction to the sequential sweep when priorities fall
- * with the vertex id on a clique.
+ * synchronous and colour-ordered iterations are pinned by hand-worked cases,
+ * invariants and a brute-force recomputation of whole iterations on small
+ * graphs (gains from the pairwise form of modularity, rounds from the
+ * generator module's SplitMix64, the decision rule restated); the colouring
+ * is pinned by its defining properties (proper, greedy-minimal in priority
+ * order) and the colour-ordered iteration also by its reduction to the
+ * sequential sweep when priorities fall with the vertex id on a clique.
  */
 #include <stdint.h>
 #include <stdlib.h>
