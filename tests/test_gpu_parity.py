@@ -193,6 +193,20 @@ def test_det_hub_bins():
     det_parity(hub_graph())
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_det_and_coloured_random_graphs(seed):
+    # ragged random graphs (sizes that leave partial tiles in every bin, self-loops,
+    # weights up to 9, isolated vertices) in both deterministic modes and round settings
+    rng = np.random.default_rng(4200 + seed)
+    n = int(rng.integers(150, 1500))
+    e, w = random_graph(rng, n, float(rng.uniform(2.0, 30.0)) / n, wmax=9, self_loops=True)
+    e += [(0, v) for v in range(1, min(n, 40 + 120 * seed))]  # one long row
+    w += [int(x) for x in rng.integers(1, 10, size=min(n, 40 + 120 * seed) - 1)]
+    csr = graphgen.from_edges(n, e, w, name="rand%d" % seed)
+    det_parity(csr, round_bits=seed % 3, seed=seed)
+    det_parity(csr, coloured=True, seed=seed)
+
+
 # ----------------------------------------------------------------- colour-ordered mode
 
 @pytest.mark.parametrize("idx", range(6))
