@@ -196,7 +196,8 @@ def test_det_hub_bins():
 @pytest.mark.parametrize("seed", range(6))
 def test_det_and_coloured_random_graphs(seed):
     # ragged random graphs (sizes that leave partial tiles in every bin, self-loops,
-    # weights up to 9, isolated vertices) in both deterministic modes and round settings
+    # weights up to 9, isolated vertices) in both deterministic modes and round settings,
+    # and in fast mode
     rng = np.random.default_rng(4200 + seed)
     n = int(rng.integers(150, 1500))
     e, w = random_graph(rng, n, float(rng.uniform(2.0, 30.0)) / n, wmax=9, self_loops=True)
@@ -205,6 +206,12 @@ def test_det_and_coloured_random_graphs(seed):
     csr = graphgen.from_edges(n, e, w, name="rand%d" % seed)
     det_parity(csr, round_bits=seed % 3, seed=seed)
     det_parity(csr, coloured=True, seed=seed)
+    # fast mode: a valid partition whose reported Q is the oracle's Q of it, bit for bit
+    import paper_2312_04876_amd as P
+    memb, q, _ = P.louvain(*to_device(csr), mode="fast")
+    memb = memb.cpu().numpy()
+    assert is_valid_partition(memb)
+    assert q == oracle.modularity(_og(csr), memb)
 
 
 # ----------------------------------------------------------------- colour-ordered mode
