@@ -81,7 +81,8 @@ static uint64_t splitmix_mix(uint64_t z)
     return z ^ (z >> 31);
 }
 
-/* The synchronous iteration's round of vertex i in iteration l of pass p. */
+/* The synchronous iteration's round of vertex i in iteration l of pass p (the
+ * hashed-round reading of the synchronous mode, which the paper does not have). */
 static int32_t sync_round(uint64_t seed, int32_t sample_bits, int32_t p, int32_t l, int32_t i)
 {
     if (sample_bits <= 0) return 0;
@@ -91,7 +92,8 @@ static int32_t sync_round(uint64_t seed, int32_t sample_bits, int32_t p, int32_t
     return (int32_t)(x >> (64 - sample_bits));
 }
 
-/* Priority of vertex v in pass p for the colouring (distinct for distinct v). */
+/* Priority of vertex v in pass p for the colouring of the colour-ordered reading
+ * (distinct for distinct v). */
 static uint64_t colour_priority(uint64_t seed, int32_t p, int32_t v)
 {
     uint64_t ctr = (1ULL << 63) | ((uint64_t)(uint32_t)p << 40) | (uint64_t)(uint32_t)v;
@@ -194,7 +196,7 @@ int oracle_modularity_exact(int32_t n, const int64_t *off, const int32_t *tgt,
     return 0;
 }
 
-/* Q as a double: (double)num / (double)den, and 0 for an edgeless graph. */
+/* Eq. 1 as a double: (double)num / (double)den, and 0 for an edgeless graph. */
 double oracle_modularity(int32_t n, const int64_t *off, const int32_t *tgt,
                          const int64_t *w, const int32_t *C)
 {
@@ -720,6 +722,7 @@ int32_t oracle_louvain_from(int32_t mode, int32_t max_passes, int32_t max_iter,
     return rc == 0 ? passes : rc;
 }
 
+/* Alg. 1 from singletons (oracle_louvain_from without a warm start). */
 int32_t oracle_louvain(int32_t mode, int32_t max_passes, int32_t max_iter,
                        int32_t prune, double tolerance, double tolerance_drop,
                        double aggregation_tolerance, uint64_t seed,
