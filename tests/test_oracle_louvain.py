@@ -122,3 +122,43 @@ def test_sbm_recovers_planted_quality():
     planted = oracle.modularity(g, graphgen.sbm_blocks(10000, 100))
     _, q, _ = oracle.louvain(g, oracle.Params(mode="seq"))
     assert q > planted - 0.1
+
+
+@pytest.mark.parametrize("wl", ["sbm10k", "rmat12-8"])
+@pytest.mark.parametrize("mp", [1, 2, 3])
+@pytest.mark.parametrize("mode", ["seq", "sync"])
+def test_pass_limit_lookup_applies_each_pass_once(wl, mp, mode):
+    # Alg. 1 when the pass loop runs out of passes (reading g4): the membership is the
+    # composition of each pass's renumbered labels, applied once per pass.  The
+    # composition is rebuilt here from single steps (one local-moving phase per level,
+    # numpy's dense renumbering, the aggregated level) and must equal the C pass loop's
+    # result; Q(G, membership) must equal the modularity of the last aggregated level
+    # under singletons.
+    g = _og(graphgen.workload(wl))
+    # R-MAT levels shrink by less than the 0.8 test after two passes; an aggregation
+    # tolerance of 1 keeps its loop going so that the pass limit is what ends it
+    prm = oracle.Params(mode=mode, max_passes=mp,
+                        aggregation_tolerance=1.0 if wl.startswith("rmat") else 0.8)
+    memb, q, rec = oracle.louvain(g, prm)
+    assert rec["passes"] == mp
+    top = np.arange(g.n)
+    level, tau = g, prm.tolerance
+    for p in range(mp):
+        st = oracle.MoveState.fresh(level)
+        tr = oracle.move(level, st, mode, tau, prm.max_iterations, prm.prune, prm.seed, p,
+                         prm.sample_bits)
+        nc = len(np.unique(st.C))
+        # the loop runs on: no pass stops by convergence or by too few merges
+        assert tr.iterations > 1 and nc / level.n <= prm.aggregation_tolerance, (wl, p)
+        dense = np.unique(st.C, return_inverse=True)[1].astype(np.int32)
+        top = dense[top]
+        level = oracle.aggregate(level, dense, nc)
+        tau = tau / prm.tolerance_drop
+    assert np.array_equal(memb, top)
+    assert q == oracle.modularity(level, np.arange(level.n, dtype=np.int32))
+    assert q == oracle.modularity(g, top)
+    # the membership pin fails for a double lookup of the last pass's labels (renumbered
+    # as the loop's result is); Q alone may not see it, since merging communities of
+    # isolated vertices (Sigma 0) leaves Q unchanged
+    twice = np.unique(dense[top], return_inverse=True)[1]
+    assert not np.array_equal(memb, twice)
