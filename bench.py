@@ -46,8 +46,7 @@ def parse():
                     help="pick the hub threshold and hub partition size by timing the candidates "
                          "on this workload first (paper_2312_04876_amd.autotune)")
     ap.add_argument("--round-bits", type=int, default=None,
-                    help="2^round_bits rounds per iteration (default 1; 2 for fast-mode batches and "
-                         "serving, where 2 rounds let some graphs of a large union collapse)")
+                    help="2^round_bits rounds per iteration (default 1)")
     ap.add_argument("--cpu-baseline", default="same",
                     help="workload the oracle is timed on: 'same' (the benchmark workload, "
                          "one whole run), a workload name, or 'none'")
@@ -459,9 +458,7 @@ def dynamic_main(args):
 def main():
     args = parse()
     if args.round_bits is None:
-        # a large union in fast mode needs 4 rounds per iteration: with 2, some of its small
-        # graphs collapse to a few communities (measured on the SBM batch recipe)
-        args.round_bits = 2 if (args.batch or args.serve) and args.mode == "fast" else 1
+        args.round_bits = 1
     if args.dynamic:
         if args.gpus != 1:
             print("bench.py measures one GPU; use --gpus 1", file=sys.stderr)

@@ -85,17 +85,25 @@ __device__ inline bool decide(const MoveArgs<C> &a, int64_t W, int dc, typename 
     return true;
 }
 
-// Fast mode applies a move at once: label, both community weights and both
-// sizes (HBM atomics), so every vertex decided later reads the new state.
+// Fast mode applies a move at once: both community weights and both sizes
+// (HBM atomics), then the label, so every vertex decided later reads the new
+// state.  The label goes last, after a device-scope fence: a reader that
+// sees the new label of a neighbour must not score its new community
+// against a total that still lacks the neighbour's weight (with the label
+// ahead of the totals, every such reader over-rates the mover's community
+// and under-rates its old one, and movers pull their neighbours after them;
+// a CPU model of that delay loses 0.04-0.06 of Q on a heavy-weight R-MAT
+// graph, against under 0.001 when both are published together).
 template <class C>
 __device__ inline void fast_apply(const MoveArgs<C> &a, int v, int dc, int bc, typename C::ST kv)
 {
     typedef typename C::ST ST;
-    a.Cp[v] = bc;
     atomic_add_t<ST>(&a.Sig[dc], (ST)-kv);
     atomic_add_t<ST>(&a.Sig[bc], kv);
     atomicSub(&a.size[dc], 1);
     atomicAdd(&a.size[bc], 1);
+    __threadfence();
+    a.Cp[v] = bc;
 }
 
 // Commits the moves decided by the lanes with m set (one lane per vertex);
@@ -142,10 +150,13 @@ __device__ inline void record_move(const MoveArgs<C> &a, int v, int dc, int bc,
 
 // Fast mode, bins 0-3: a workgroup adds the community weight and size changes
 // of its moves into an LDS table and applies them with one HBM atomic per
-// community every few steps.  A GPU decides thousands of vertices against
-// the same state anyway, so this adds little delay, while it folds the many
-// moves into one popular community (atomics performed at the memory side,
-// each also evicting the line every scoring lane reads) into a few.
+// community every few steps; the movers' labels wait in an LDS list and are
+// published after those atomics, so labels and totals become visible together
+// (labels never ahead of the totals, see fast_apply).  A GPU decides
+// thousands of vertices against the same state anyway, so this adds little
+// delay, while it folds the many moves into one popular community (atomics
+// performed at the memory side, each also evicting the line every scoring
+// lane reads) into a few.
 template <typename ST>
 __device__ inline void pending_add(int32_t *keys, ST *dsig, int32_t *dsz, int log2s, int32_t c,
                                    ST dk, int ds)
@@ -165,9 +176,12 @@ __device__ inline void pending_add(int32_t *keys, ST *dsig, int32_t *dsz, int lo
     atomicAdd(&dsz[h], ds);
 }
 
+// Publishes the pending totals, then the pending labels (mv_v[k] -> mv_c[k]
+// for k < *mv_n); every thread of the workgroup calls this between barriers.
 template <class C>
 __device__ inline void pending_flush(const MoveArgs<C> &a, int32_t *keys, typename C::ST *dsig,
-                                     int32_t *dsz, int slots)
+                                     int32_t *dsz, int slots, const int32_t *mv_v,
+                                     const int32_t *mv_c, int32_t *mv_n)
 {
     typedef typename C::ST ST;
     for (int q = threadIdx.x; q < slots; q += blockDim.x) {
@@ -179,6 +193,13 @@ __device__ inline void pending_flush(const MoveArgs<C> &a, int32_t *keys, typena
         dsig[q] = 0;
         dsz[q] = 0;
     }
+    const int nm = *mv_n;
+    if (nm == 0) return;  // uniform: read by every thread before the barrier below
+    __threadfence();      // the totals are performed before any label is stored
+    __syncthreads();
+    for (int k = threadIdx.x; k < nm; k += blockDim.x) a.Cp[mv_v[k]] = mv_c[k];
+    __syncthreads();
+    if (threadIdx.x == 0) *mv_n = 0;
 }
 
 // Counter row of the calling wavefront.
@@ -283,6 +304,9 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
     __shared__ int32_t p_keys[PS];
     __shared__ ST p_sig[PS];
     __shared__ int32_t p_sz[PS];
+    constexpr int PM = FAST ? NG * FL : 1;  // movers of one flush window
+    __shared__ int32_t p_mv[PM], p_mc[PM];
+    __shared__ int32_t p_nm;
     if (*a.done) return;
     const int count = *a.count;
     if (count == 0) return;
@@ -294,12 +318,14 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
         keys[q] = -1;
         vals[q] = 0;
     }
-    if (FAST)
+    if (FAST) {
         for (int q = threadIdx.x; q < PS; q += 256) {
             p_keys[q] = -1;
             p_sig[q] = 0;
             p_sz[q] = 0;
         }
+        if (threadIdx.x == 0) p_nm = 0;
+    }
     __syncthreads();
     SC gain_acc = 0;
     unsigned long long nv = 0, ne = 0, nk = 0, nm = 0;
@@ -400,13 +426,15 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
         }
         if (FAST) {
             if (mv && gl == 0) {
-                a.Cp[v] = bc;
+                const int k = atomicAdd(&p_nm, 1);  // < NG * FL: one row per group and step
+                p_mv[k] = v;
+                p_mc[k] = bc;
                 pending_add<ST>(p_keys, p_sig, p_sz, PLOG2, dc, (ST)-kv, -1);
                 pending_add<ST>(p_keys, p_sig, p_sz, PLOG2, bc, kv, 1);
             }
             if (step % FL == FL - 1 || b0 + stride >= count) {  // uniform over the block
                 __syncthreads();
-                pending_flush<C>(a, p_keys, p_sig, p_sz, PS);
+                pending_flush<C>(a, p_keys, p_sig, p_sz, PS, p_mv, p_mc, &p_nm);
                 __syncthreads();
             }
         } else {

@@ -39,7 +39,7 @@ def same_graph(a, b) -> bool:
 
 
 def is_valid_partition(memb: np.ndarray) -> bool:
-    """Dense labels 0..k-1, each used, assigned in order of first use of the old labels."""
+    """Dense labels: every label in 0..k-1 is used by some vertex."""
     if memb.size == 0:
         return True
     k = int(memb.max()) + 1
@@ -59,3 +59,28 @@ def heavy(csr, seed, wmax=1 << 24, name=""):
                               name=name or (csr.name + "-heavy"))
     assert int(out.weights.sum(dtype=np.int64)) >= 1 << 31
     return out
+
+
+def relabelled(g, perm):
+    """The oracle graph g with vertex v renamed perm[v] (rows keep their entries)."""
+    n = g.n
+    deg = np.diff(g.offsets)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum(deg[inv])
+    rows = np.concatenate([np.arange(g.offsets[v], g.offsets[v + 1]) for v in inv]) \
+        if g.nnz else np.zeros(0, dtype=np.int64)
+    return oracle.Graph(n, off, perm[g.targets[rows]].astype(np.int32), g.weights[rows].copy())
+
+
+def seq_floor(g, orders=8, seed=0):
+    """Lowest modularity the sequential oracle reaches on g over its own vertex order and
+    `orders` random relabellings of g (the same graph visited in other orders): the
+    spread of the asynchronous method itself, which the 0.01 band of fast mode sits on."""
+    q = oracle.louvain(g, oracle.Params(mode="seq"))[1]
+    rng = np.random.default_rng(seed)
+    for _ in range(orders):
+        perm = rng.permutation(g.n).astype(np.int64)
+        q = min(q, oracle.louvain(relabelled(g, perm), oracle.Params(mode="seq"))[1])
+    return q

@@ -16,7 +16,7 @@ import pytest
 
 import graphgen
 import oracle
-from gpu_util import canonical, heavy, is_valid_partition, same_graph, to_device
+from gpu_util import canonical, heavy, is_valid_partition, same_graph, seq_floor, to_device
 from refs import random_graph
 
 pytestmark = pytest.mark.gpu
@@ -176,17 +176,38 @@ def test_coloured_wide_totals():
     det_parity(heavy(hub_graph(), 4), coloured=True, seed=1)
 
 
-def test_fast_wide_totals():
+def _row_sum_max(csr):
+    src = np.repeat(np.arange(csr.n), np.diff(csr.offsets))
+    return np.bincount(src, weights=csr.weights.astype(np.float64), minlength=csr.n).max()
+
+
+# heavy-weight graphs (W past 2^31): random weights make every vertex's heaviest edge a
+# strong pull, the case where a label seen before its community total is updated
+# drags neighbours after movers
+FAST_HEAVY = {
+    "rmat13-8": lambda: heavy(graphgen.rmat(13, 8, seed=43), 5),
+    "rmat12-16": lambda: heavy(graphgen.rmat(12, 16, seed=7), 11),
+    "rmat14-8": lambda: heavy(graphgen.rmat(14, 8, seed=44), 6),
+    "sbm10k-w16": lambda: heavy(graphgen.workload("sbm10k"), 8, wmax=1 << 16),
+}
+
+
+@pytest.mark.parametrize("name", sorted(FAST_HEAVY))
+def test_fast_wide_totals(name):
     import paper_2312_04876_amd as P
-    csr = heavy(graphgen.rmat(13, 8, seed=43), 5)
+    csr = FAST_HEAVY[name]()
+    # rows past 2^31 take the 64-bit LDS tables; the SBM keeps every row below it (32-bit)
+    assert (_row_sum_max(csr) >= 2.0 ** 31) == name.startswith("rmat"), name
     g = _og(csr)
     off, tgt, w = to_device(csr)
-    memb, q, _ = P.louvain(off, tgt, w, mode="fast")
-    memb = memb.cpu().numpy()
-    assert is_valid_partition(memb)
-    assert q == oracle.modularity(g, memb)
     _, q_seq, _ = oracle.louvain(g, oracle.Params(mode="seq"))
-    assert abs(q - q_seq) <= 0.01
+    for rep in range(3):
+        memb, q, _ = P.louvain(off, tgt, w, mode="fast")
+        memb = memb.cpu().numpy()
+        print("fast", name, "run", rep, "Q %.5f sequential oracle %.5f" % (q, q_seq), flush=True)
+        assert is_valid_partition(memb)
+        assert q == oracle.modularity(g, memb)
+        assert abs(q - q_seq) <= 0.01, (name, rep, q, q_seq)
 
 
 def test_det_hub_bins():
@@ -206,12 +227,15 @@ def test_det_and_coloured_random_graphs(seed):
     csr = graphgen.from_edges(n, e, w, name="rand%d" % seed)
     det_parity(csr, round_bits=seed % 3, seed=seed)
     det_parity(csr, coloured=True, seed=seed)
-    # fast mode: a valid partition whose reported Q is the oracle's Q of it, bit for bit
+    # fast mode: a valid partition whose reported Q is the oracle's Q of it, bit for bit,
+    # no more than 0.01 below the sequential oracle over its own vertex order and eight
+    # relabellings (small random graphs spread more than 0.01 over visiting orders)
     import paper_2312_04876_amd as P
     memb, q, _ = P.louvain(*to_device(csr), mode="fast")
     memb = memb.cpu().numpy()
     assert is_valid_partition(memb)
     assert q == oracle.modularity(_og(csr), memb)
+    assert q >= seq_floor(_og(csr)) - 0.01
 
 
 # ----------------------------------------------------------------- colour-ordered mode
