@@ -49,57 +49,87 @@ COLOUR = 2
 _MODES = {"sync": SYNC, "seq": SEQ, "colour": COLOUR}
 
 
+_LIB_TIMING = os.path.join(_HERE, "liblouvain_oracle_omp.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction, one thread)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-             "-Wall", "-Wextra", "-Wno-unused-parameter", _SRC, "-o", tmp])
+             "-Wall", "-Wextra", "-Wno-unused-parameter", "-Wno-unknown-pragmas", _SRC,
+             "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
 
 
+def build_timing() -> str:
+    """Compile the CPU-baseline build of the same source on the machine that will run it:
+    -O3 -march=native, OpenMP on (the decisions of a synchronous round run on every
+    thread; the results are those of the serial build), still no contraction."""
+    tmp = _LIB_TIMING + ".tmp%d" % os.getpid()
+    subprocess.check_call(
+        ["gcc", "-std=gnu11", "-O3", "-march=native", "-fopenmp", "-ffp-contract=off", "-fPIC",
+         "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter", _SRC, "-o", tmp])
+    os.replace(tmp, _LIB_TIMING)
+    return _LIB_TIMING
+
+
 _lib = None
+_lib_timing = None
+
+
+def timing_library():
+    """The -O3 -march=native OpenMP build (compiled here on first use); pass it as `lib=`
+    to move() or louvain()."""
+    global _lib_timing
+    if _lib_timing is None:
+        _lib_timing = _bind(ctypes.CDLL(build_timing()))
+    return _lib_timing
 
 
 def _load():
     global _lib
     if _lib is None:
         build(force=False)
-        lib = ctypes.CDLL(_LIB)
-        i32, i64, u64, dbl, vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
-                                  ctypes.c_double, ctypes.c_void_p)
-        lib.oracle_vertex_weights.restype = i64
-        lib.oracle_vertex_weights.argtypes = [i32, vp, vp, vp]
-        lib.oracle_modularity_exact.restype = ctypes.c_int
-        lib.oracle_modularity_exact.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp]
-        lib.oracle_modularity.restype = dbl
-        lib.oracle_modularity.argtypes = [i32, vp, vp, vp, vp]
-        lib.oracle_move_gain.restype = ctypes.c_int
-        lib.oracle_move_gain.argtypes = [i32, vp, vp, vp, vp, i32, i32, vp, vp]
-        lib.oracle_move.restype = i32
-        lib.oracle_move.argtypes = [i32, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp,
-                                    i32, dbl, i32, u64, i32, i32, vp, vp, vp, vp]
-        lib.oracle_renumber.restype = i32
-        lib.oracle_renumber.argtypes = [i32, vp]
-        lib.oracle_community_vertices.restype = None
-        lib.oracle_community_vertices.argtypes = [i32, vp, i32, vp, vp]
-        lib.oracle_aggregate.restype = i64
-        lib.oracle_aggregate.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp, i64]
-        lib.oracle_louvain.restype = i32
-        lib.oracle_louvain.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, u64, i32, i32, vp,
-                                       vp, vp, vp, vp, vp, vp, vp]
-        lib.oracle_colour.restype = i32
-        lib.oracle_colour.argtypes = [i32, vp, vp, u64, i32, vp]
-        lib.oracle_move_coloured.restype = i32
-        lib.oracle_move_coloured.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, i32, dbl,
-                                             i32, vp, i32, vp, vp, vp, vp]
-        lib.oracle_louvain_from.restype = i32
-        lib.oracle_louvain_from.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, u64, i32, i32,
-                                            vp, vp, vp, vp, vp, vp, vp, vp, vp]
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _bind(lib):
+    """Argument and result types of the oracle's C entry points on a loaded build."""
+    i32, i64, u64, dbl, vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                              ctypes.c_double, ctypes.c_void_p)
+    lib.oracle_vertex_weights.restype = i64
+    lib.oracle_vertex_weights.argtypes = [i32, vp, vp, vp]
+    lib.oracle_modularity_exact.restype = ctypes.c_int
+    lib.oracle_modularity_exact.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.oracle_modularity.restype = dbl
+    lib.oracle_modularity.argtypes = [i32, vp, vp, vp, vp]
+    lib.oracle_move_gain.restype = ctypes.c_int
+    lib.oracle_move_gain.argtypes = [i32, vp, vp, vp, vp, i32, i32, vp, vp]
+    lib.oracle_move.restype = i32
+    lib.oracle_move.argtypes = [i32, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp,
+                                i32, dbl, i32, u64, i32, i32, vp, vp, vp, vp]
+    lib.oracle_renumber.restype = i32
+    lib.oracle_renumber.argtypes = [i32, vp]
+    lib.oracle_community_vertices.restype = None
+    lib.oracle_community_vertices.argtypes = [i32, vp, i32, vp, vp]
+    lib.oracle_aggregate.restype = i64
+    lib.oracle_aggregate.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp, i64]
+    lib.oracle_louvain.restype = i32
+    lib.oracle_louvain.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, u64, i32, i32, vp,
+                                   vp, vp, vp, vp, vp, vp, vp]
+    lib.oracle_colour.restype = i32
+    lib.oracle_colour.argtypes = [i32, vp, vp, u64, i32, vp]
+    lib.oracle_move_coloured.restype = i32
+    lib.oracle_move_coloured.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, i32, dbl,
+                                         i32, vp, i32, vp, vp, vp, vp]
+    lib.oracle_louvain_from.restype = i32
+    lib.oracle_louvain_from.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, u64, i32, i32,
+                                        vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    return lib
 
 
 def _p(a: np.ndarray):
@@ -229,7 +259,7 @@ def colour(g: Graph, seed: int = 0, pass_index: int = 0) -> Tuple[np.ndarray, in
 
 def move(g: Graph, st: MoveState, mode: str = "seq", tau: float = 0.01, max_iter: int = 20,
          prune: bool = True, seed: int = 0, pass_index: int = 0,
-         sample_bits: int = 1) -> MoveTrace:
+         sample_bits: int = 1, lib=None) -> MoveTrace:
     """Alg. 2 (louvainMove) in place on ``st``; returns sweeps run and per-sweep traces.
 
     ``seed``, ``pass_index`` and ``sample_bits`` split a synchronous iteration into
@@ -243,15 +273,16 @@ def move(g: Graph, st: MoveState, mode: str = "seq", tau: float = 0.01, max_iter
     for a, dt in ((st.K, np.int64), (st.Sigma, np.int64), (st.C, np.int32), (st.size, np.int32),
                   (st.active, np.uint8)):
         assert a.dtype == dt and a.flags.c_contiguous and a.shape == (g.n,)
+    lib = lib or _load()
     if mode == "colour":
         col, k = colour(g, seed, pass_index)
         col = np.ascontiguousarray(col if g.n else np.zeros(1, dtype=np.int32))
-        l = _load().oracle_move_coloured(g.n, _p(g.offsets), _p(g.targets), _p(g.weights),
+        l = lib.oracle_move_coloured(g.n, _p(g.offsets), _p(g.targets), _p(g.weights),
                                          _p(st.K), st.W, _p(st.Sigma), _p(st.C), _p(st.size),
                                          _p(st.active), 1 if prune else 0, float(tau),
                                          int(max_iter), _p(col), k, _p(hi), _p(lo), _p(mv), _p(pr))
     else:
-        l = _load().oracle_move(_MODES[mode], g.n, _p(g.offsets), _p(g.targets), _p(g.weights),
+        l = lib.oracle_move(_MODES[mode], g.n, _p(g.offsets), _p(g.targets), _p(g.weights),
                                 _p(st.K), st.W, _p(st.Sigma), _p(st.C), _p(st.size),
                                 _p(st.active), 1 if prune else 0, float(tau), int(max_iter),
                                 int(seed) & ((1 << 64) - 1), int(pass_index), int(sample_bits),
@@ -291,7 +322,7 @@ def aggregate(g: Graph, C, nc: int) -> Graph:
                                    int(nc), _p(off), _p(tgt), _p(w), cap)
     if got < 0:
         raise RuntimeError("oracle_aggregate failed")
-    return Graph(int(nc), off, tgt[:got].copy(), w[:got].copy())
+    return Graph(int(nc), off, tgt[:got], w[:got])  # views: no second copy of a large level
 
 
 @dataclass
@@ -308,9 +339,10 @@ class Params:
     sample_bits: int = 1   # a synchronous iteration runs in 2**sample_bits rounds
 
 
-def louvain(g: Graph, params: Optional[Params] = None, initial=None):
+def louvain(g: Graph, params: Optional[Params] = None, initial=None, lib=None):
     """Alg. 1 entirely in C. Returns (membership int32[n], Q, records dict).
-    ``initial``: labels of a partition the first pass starts from (a warm start)."""
+    ``initial``: labels of a partition the first pass starts from (a warm start).
+    ``lib``: another build of the oracle (timing_library()); the serial build by default."""
     p = params or Params()
     mp = max(p.max_passes, 1)
     memb = np.zeros(max(g.n, 1), dtype=np.int32)
@@ -323,7 +355,7 @@ def louvain(g: Graph, params: Optional[Params] = None, initial=None):
         init = np.ascontiguousarray(initial, dtype=np.int32)
         if init.shape != (g.n,) or (g.n and (init.min() < 0 or init.max() >= g.n)):
             raise ValueError("initial labels must be n values in [0, n)")
-    passes = _load().oracle_louvain_from(_MODES[p.mode], p.max_passes, p.max_iterations,
+    passes = (lib or _load()).oracle_louvain_from(_MODES[p.mode], p.max_passes, p.max_iterations,
                                          1 if p.prune else 0, p.tolerance, p.tolerance_drop,
                                          p.aggregation_tolerance, int(p.seed) & ((1 << 64) - 1),
                                          int(p.sample_bits), g.n, _p(g.offsets), _p(g.targets),

@@ -62,6 +62,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef __int128 i128;
 
@@ -400,8 +403,22 @@ static int32_t move_impl(int32_t mode, int32_t n, const int64_t *off,
     int32_t *mv_c = (int32_t *)malloc(m * sizeof(int32_t));
     i128 *mv_N = (i128 *)malloc(m * sizeof(i128));
     uint8_t *mark = (uint8_t *)malloc(m);
-    if (table_init(&t, n) != 0 || !C0 || !S0 || !z0 || !mv_i || !mv_c || !mv_N || !mark) {
+    /* one scan table per thread for the decisions of a synchronous round
+     * (a single table without OpenMP) */
+#ifdef _OPENMP
+    const int nt = mode == ORACLE_SEQ ? 1 : omp_get_max_threads();
+#else
+    const int nt = 1;
+#endif
+    scan_table *tt = (scan_table *)calloc((size_t)nt, sizeof(scan_table));
+    int tables_ok = tt != NULL;
+    for (int k = 0; tt && k < nt; ++k)
+        if (table_init(&tt[k], n) != 0) tables_ok = 0;
+    if (table_init(&t, n) != 0 || !tables_ok || !C0 || !S0 || !z0 || !mv_i || !mv_c || !mv_N ||
+        !mark) {
         table_free(&t);
+        for (int k = 0; tt && k < nt; ++k) table_free(&tt[k]);
+        free(tt);
         free(C0); free(S0); free(z0); free(mv_i); free(mv_c); free(mv_N); free(mark);
         return -1;
     }
@@ -439,30 +456,44 @@ static int32_t move_impl(int32_t mode, int32_t n, const int64_t *off,
                 memcpy(C0, C, (size_t)n * sizeof(int32_t));
                 memcpy(S0, Sig, (size_t)n * sizeof(int64_t));
                 memcpy(z0, size, (size_t)n * sizeof(int32_t));
-                int32_t nm = 0;
+                /* every decision of the round reads only the snapshot (C0, S0, z0),
+                 * so the decisions are independent: vertex i's choice goes to
+                 * mv_c[i] (-1 to stay) and its gain to mv_N[i].  A build with
+                 * OpenMP takes them on several threads; the moves are then listed
+                 * and applied in ascending vertex order either way. */
+                int32_t nproc = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : nproc)
                 for (int32_t i = 0; i < n; ++i) {
+                    mv_c[i] = -1;
                     if (!active[i]) continue;
                     if ((colour ? colour[i] : sync_round(seed, sample_bits, pass_index, it, i)) != r)
                         continue;
                     active[i] = 0;
-                    ++processed;
+                    ++nproc;
+#ifdef _OPENMP
+                    scan_table *ti = &tt[omp_get_thread_num()];
+#else
+                    scan_table *ti = &tt[0];
+#endif
                     int32_t c;
                     i128 N;
-                    if (decide(&t, off, tgt, w, K, W, C0, S0, z0, colour ? 0 : 1, i, &c, &N)) {
-                        mv_i[nm] = i;
-                        mv_c[nm] = c;
-                        mv_N[nm] = N;
-                        ++nm;
+                    if (decide(ti, off, tgt, w, K, W, C0, S0, z0, colour ? 0 : 1, i, &c, &N)) {
+                        mv_c[i] = c;
+                        mv_N[i] = N;
                     }
                 }
+                processed += nproc;
+                int32_t nm = 0;
+                for (int32_t i = 0; i < n; ++i)
+                    if (mv_c[i] >= 0) mv_i[nm++] = i;
                 for (int32_t k = 0; k < nm; ++k) {
-                    int32_t i = mv_i[k], c = mv_c[k], d = C[i];
+                    int32_t i = mv_i[k], c = mv_c[i], d = C[i];
                     Sig[d] -= K[i];
                     Sig[c] += K[i];
                     size[d] -= 1;
                     size[c] += 1;
                     C[i] = c;
-                    sumN += mv_N[k];
+                    sumN += mv_N[i];
                     for (int64_t e = off[i]; e < off[i + 1]; ++e) mark[tgt[e]] = 1;
                 }
                 moves += nm;
@@ -476,6 +507,8 @@ static int32_t move_impl(int32_t mode, int32_t n, const int64_t *off,
         if (iteration_dq(sumN, W) <= tau) break;
     }
     table_free(&t);
+    for (int k = 0; k < nt; ++k) table_free(&tt[k]);
+    free(tt);
     free(C0); free(S0); free(z0); free(mv_i); free(mv_c); free(mv_N); free(mark);
     return l;
 }
@@ -563,7 +596,7 @@ int64_t oracle_aggregate(int32_t n, const int64_t *off, const int32_t *tgt,
                          int64_t *out_off, int32_t *out_tgt, int64_t *out_w,
                          int64_t cap)
 {
-    scan_table t;
+    scan_table t = {0};
     int64_t *coff = (int64_t *)malloc((size_t)(nc + 1) * sizeof(int64_t));
     int32_t *members = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
     if (!coff || !members || table_init(&t, nc) != 0) {

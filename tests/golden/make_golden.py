@@ -9,6 +9,8 @@ spread of sequential-mode Q over random vertex relabellings, which calibrates
 the fast-mode tolerance.
 
 Usage: python tests/golden/make_golden.py [--only colour] [workload ...]
+       python tests/golden/make_golden.py --full rmat24   (pass-by-pass records of a
+       workload whose levels are too large for the oracle's own pass loop)
 """
 import hashlib
 import json
@@ -21,9 +23,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
+sys.path.insert(0, HERE)
 
 import graphgen  # noqa: E402
 import oracle  # noqa: E402
+from digest import graph_digest, labels_digest  # noqa: E402
 
 OUT = os.path.join(HERE, "reference.json")
 DEFAULT = ["sbm10k", "rmat16-16", "rmat18-16", "rmat22", "sbm1m"]
@@ -85,8 +89,85 @@ def run(name: str, spread_orders: int, only=None, old=None):
     return rec
 
 
+def lean_louvain(g, prm, lib=None, log=print):
+    """Alg. 1 over the oracle's single steps (local moving, renumbering, aggregation)
+    without keeping the levels, for graphs whose levels do not fit in memory twice:
+    the pass loop of oracle.louvain_trace.  Returns (membership, Q, per-pass records:
+    the local-moving trace, a digest of the raw labels, the communities and a digest of
+    the aggregated level)."""
+    top = np.arange(g.n, dtype=np.int32)
+    level, tau, broke, Cp = g, prm.tolerance, False, None
+    passes = []
+    for p in range(prm.max_passes):
+        t = time.time()
+        st = oracle.MoveState.fresh(level)
+        tr = oracle.move(level, st, prm.mode, tau, prm.max_iterations, prm.prune, prm.seed, p,
+                         prm.sample_bits, lib=lib)
+        Cp = st.C
+        del st
+        nc = int(np.unique(Cp).size) if level.n else 0
+        rec = {"vertices": level.n, "entries": level.nnz, "iterations": tr.iterations,
+               "sumN": [str(x) for x in tr.sumN], "moves": tr.moves, "processed": tr.processed,
+               "labels": labels_digest(Cp), "communities": nc}
+        passes.append(rec)
+        log("  pass %d: %d vertices, %d iterations, %d communities (%.0f s)" %
+            (p, level.n, tr.iterations, nc, time.time() - t))
+        if tr.iterations <= 1 or float(nc) / float(level.n) > prm.aggregation_tolerance:
+            broke = True
+            break
+        Cp, nc = oracle.renumber(Cp)
+        top = Cp[top]
+        t = time.time()
+        nxt = oracle.aggregate(level, Cp, nc)
+        rec["next_level"] = graph_digest(nxt.offsets, None, nxt.targets, nxt.weights)
+        log("  aggregated: %d vertices, %d entries (%.0f s)" % (nxt.n, nxt.nnz, time.time() - t))
+        level = nxt
+        tau = tau / prm.tolerance_drop
+    if broke:
+        top = Cp[top]
+    memb, _ = oracle.renumber(top)
+    return memb, oracle.modularity(g, memb), passes
+
+
+def full_record(name: str):
+    """Records of a workload too large for oracle.louvain's level buffers (R-MAT-24): the
+    sequential run (quality reference of fast mode) and the synchronous run pass by pass
+    (bit-exact reference of deterministic mode), both through lean_louvain; the
+    synchronous run uses the OpenMP build, whose results equal the serial build's
+    (tests/test_oracle_timing_build.py)."""
+    t = time.time()
+    csr = graphgen.workload(name, threads=min(16, os.cpu_count() or 1))
+    print("generated %s: n=%d nnz=%d (%.0f s)" % (name, csr.n, csr.nnz, time.time() - t),
+          flush=True)
+    rec = {"n": csr.n, "nnz": csr.nnz, "W": int(csr.weights.sum(dtype=np.int64))}
+    g = oracle.as_graph(csr.offsets, csr.targets, csr.weights)
+    del csr
+    lib = oracle.timing_library()
+    for mode, params in (("sync", {"seed": 0, "sample_bits": 1}), ("seq", {})):
+        t = time.time()
+        print("oracle %s on %s" % (mode, name), flush=True)
+        memb, q, passes = lean_louvain(g, oracle.Params(mode=mode, **params), lib=lib,
+                                       log=lambda m: print(m, flush=True))
+        r = {"Q": q, "digest": digest(memb), "passes": len(passes),
+             "iterations": [x["iterations"] for x in passes],
+             "communities": [x["communities"] for x in passes],
+             "seconds": round(time.time() - t, 1)}
+        if mode == "sync":
+            r.update({"seed": 0, "round_bits": 1, "per_pass": passes})
+        rec[mode] = r
+        print(json.dumps({k: v for k, v in r.items() if k != "per_pass"}), flush=True)
+    return rec
+
+
 def main(argv):
     only = None
+    if argv[:1] == ["--full"]:
+        data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+        for name in argv[1:]:
+            data[name] = full_record(name)
+            with open(OUT, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+        return
     if argv[:1] == ["--only"]:
         only, argv = argv[1], argv[2:]
     names = argv or DEFAULT
