@@ -104,6 +104,11 @@ typedef struct {
                                      8192, or 4096 when wide) */
     int32_t hub_part_pairs;       /* pairs per hash partition of a hub row in local moving;
                                      1024 .. 2048 (default 2048) */
+    int32_t small_level;          /* LOUVAIN_FAST only: a level (in a batch, a graph's part of
+                                     it) of at most this many vertices is moved in vertex order
+                                     by one wavefront, the asynchronous sweep of Alg. 2 as one
+                                     thread runs it, instead of in concurrent rounds; 1 .. 1024,
+                                     0 = 1024, -1 = never */
 } louvain_params;
 
 /* Per-pass record of the last louvain_run / louvain_move / louvain_aggregate sequence. */
@@ -118,6 +123,15 @@ typedef struct {
     int64_t processed[LOUVAIN_MAX_PASSES];      /* vertex visits in each pass */
     int64_t scanned[LOUVAIN_MAX_PASSES];        /* row entries scanned by local moving in each pass */
     int32_t colours[LOUVAIN_MAX_PASSES];        /* colour classes of each level (LOUVAIN_COLOURED), else 0 */
+    /* Time of each pass by phase (Section 5.3's split), summed HIP-event times of
+     * its kernels; filled only with profile = 1 (else 0).  Moving: the
+     * local-moving kernels with their compaction, round ends and tests;
+     * aggregation: community counting, renumbering and lookup, the
+     * community-vertex CSR and the super-vertex graph; other: level setup
+     * (row sums, binning) and the final modularity (counted in the last pass). */
+    double ms_move[LOUVAIN_MAX_PASSES];
+    double ms_aggregate[LOUVAIN_MAX_PASSES];
+    double ms_other[LOUVAIN_MAX_PASSES];
 } louvain_stats;
 
 /* Timing and algorithmic traffic of one kernel family (profile = 1). */

@@ -42,6 +42,7 @@ class CParams(ctypes.Structure):
         ("aggregation_tolerance", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("round_bits", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("hub_rows", ctypes.c_int32), ("hub_part_pairs", ctypes.c_int32),
+        ("small_level", ctypes.c_int32),
     ]
 
 
@@ -57,6 +58,9 @@ class CStats(ctypes.Structure):
         ("processed", ctypes.c_int64 * MAX_PASSES),
         ("scanned", ctypes.c_int64 * MAX_PASSES),
         ("colours", ctypes.c_int32 * MAX_PASSES),
+        ("ms_move", ctypes.c_double * MAX_PASSES),
+        ("ms_aggregate", ctypes.c_double * MAX_PASSES),
+        ("ms_other", ctypes.c_double * MAX_PASSES),
     ]
 
     def as_dict(self) -> Dict[str, list]:
@@ -88,6 +92,11 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("liblouvain.so is not built (run paper_2312_04876_amd.build.build())")
+    # PyTorch first: its HIP runtime must be the one the library binds to.  Loaded the
+    # other way round, the library would pull in a second HIP runtime from the system,
+    # whose device enumeration fails beside PyTorch's, and whose streams and events are
+    # not PyTorch's.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
@@ -147,7 +156,8 @@ def _check(code: int, where: str):
 
 def make_params(mode="deterministic", max_passes=10, max_iterations=20, prune=True,
                 tolerance=0.01, tolerance_drop=10.0, aggregation_tolerance=0.8, seed=0,
-                round_bits=1, profile=False, hub_rows=0, hub_part_pairs=0) -> CParams:
+                round_bits=1, profile=False, hub_rows=0, hub_part_pairs=0,
+                small_level=0) -> CParams:
     p = CParams()
     load_library().louvain_default_params(ctypes.byref(p))
     p.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
@@ -162,6 +172,7 @@ def make_params(mode="deterministic", max_passes=10, max_iterations=20, prune=Tr
     p.profile = 1 if profile else 0
     p.hub_rows = int(hub_rows)
     p.hub_part_pairs = int(hub_part_pairs)
+    p.small_level = int(small_level)
     return p
 
 
@@ -410,3 +421,4 @@ def louvain(offsets, targets, weights, **params):
         return ctx.run()
     finally:
         ctx.close()
+

@@ -87,6 +87,11 @@ constexpr int AGG_FOLD_SLOTS = 11 * (AGG_PSLICE / 8);
 // neighbours first, so partitions are cut for several times more entries than
 // an LDS partition table holds pairs.
 constexpr int AGG_PART_ENTRIES = 4096;
+// Fast mode moves levels (in a batch: graphs) of at most SEQ_MAX vertices in
+// vertex order with one wavefront (k_seq.hip); its LDS table has 2 * SEQ_MAX
+// slots, enough for the distinct communities of any row of such a level.
+constexpr int SEQ_LOG2 = 10;
+constexpr int SEQ_MAX = 1 << SEQ_LOG2;
 // Rows per workgroup of the binning and compaction kernels.
 constexpr int BIN_CHUNK = 4096;
 // Vertices per workgroup (and LDS table slots / 2) of the community counting kernels.
@@ -262,6 +267,14 @@ __host__ __device__ inline int round_of(uint64_t seed, int round_bits, int pass,
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     return (int)(z >> (64 - round_bits));
+}
+
+// Candidate order of the delta-modularity argmax: higher score first, then
+// the lower community id.
+template <typename SC>
+__device__ inline bool better(SC s, int c, SC bs, int bc)
+{
+    return s > bs || (s == bs && c < bc);
 }
 
 // Mask of the lanes of this wavefront below the calling lane.

@@ -61,33 +61,51 @@ __device__ inline void graph_gain(const MoveArgs<C> &a, int v, typename C::SC ga
     if (a.bt.gid) atomic_add_i128(a.bt.gsum + 2 * a.bt.gid[v], (i128)gain);
 }
 
-// Candidate order: higher score first, then lower community id.
-template <typename SC>
-__device__ inline bool better(SC s, int c, SC bs, int bc)
+// A community total or size as a decision reads it.  Fast mode reads the live
+// value coherently at agent scope (past the non-coherent L1 and the per-XCD
+// L2s): movers update totals with memory-side atomics and publish labels only
+// afterwards (fast_apply), so a reader that sees a neighbour's new label and
+// then loads the total of that community (its address depends on the label)
+// sees the mover's weight in it.  A plain load could return a line its XCD
+// cached before the update, i.e. a label ahead of its total, the case that
+// drags neighbours after movers.  Deterministic mode reads the round's
+// snapshot, which no kernel of the round writes, with plain loads.
+template <bool FAST, typename T>
+__device__ inline T live_load(const T *p)
 {
-    return s > bs || (s == bs && c < bc);
+    if (FAST) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+
+// A fast-mode label store, coherent at agent scope (written through the
+// writer's L2, so readers on the other XCDs see it).
+__device__ inline void live_store(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Decision for vertex v once the group knows (best score, its community,
 // weight to the own community, non-self entries).  Returns true to move and
 // sets the gain N = best - stay.
-template <class C>
+template <class C, bool FAST>
 __device__ inline bool decide(const MoveArgs<C> &a, int64_t W, int dc, typename C::ST kv,
                               typename C::SC best, int bc, typename C::ST hd, int nonself,
                               typename C::SC *gain)
 {
     typedef typename C::SC SC;
     if (nonself <= 0 || bc == INT_MAX) return false;
-    const SC stay = (SC)W * (SC)hd - (SC)kv * ((SC)a.Sig[dc] - (SC)kv);
+    const SC stay = (SC)W * (SC)hd - (SC)kv * ((SC)live_load<FAST>(&a.Sig[dc]) - (SC)kv);
     if (!(best > stay)) return false;
-    if (a.rule && a.size[dc] == 1 && a.size[bc] == 1 && bc > dc) return false;
+    if (a.rule && live_load<FAST>(&a.size[dc]) == 1 && live_load<FAST>(&a.size[bc]) == 1 &&
+        bc > dc)
+        return false;
     *gain = best - stay;
     return true;
 }
 
 // Fast mode applies a move at once: both community weights and both sizes
 // (HBM atomics), then the label, so every vertex decided later reads the new
-// state.  The label goes last, after a device-scope fence: a reader that
+// state.  The label goes last, after an agent-scope release fence: a reader that
 // sees the new label of a neighbour must not score its new community
 // against a total that still lacks the neighbour's weight (with the label
 // ahead of the totals, every such reader over-rates the mover's community
@@ -102,8 +120,8 @@ __device__ inline void fast_apply(const MoveArgs<C> &a, int v, int dc, int bc, t
     atomic_add_t<ST>(&a.Sig[bc], kv);
     atomicSub(&a.size[dc], 1);
     atomicAdd(&a.size[bc], 1);
-    __threadfence();
-    a.Cp[v] = bc;
+    __builtin_amdgcn_s_waitcnt(0);  // the atomics have completed before the label is stored
+    live_store(&a.Cp[v], bc);
 }
 
 // Commits the moves decided by the lanes with m set (one lane per vertex);
@@ -195,9 +213,10 @@ __device__ inline void pending_flush(const MoveArgs<C> &a, int32_t *keys, typena
     }
     const int nm = *mv_n;
     if (nm == 0) return;  // uniform: read by every thread before the barrier below
-    __threadfence();      // the totals are performed before any label is stored
+    // every wave's totals have completed (vmcnt drained) before any label is stored
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int k = threadIdx.x; k < nm; k += blockDim.x) a.Cp[mv_v[k]] = mv_c[k];
+    for (int k = threadIdx.x; k < nm; k += blockDim.x) live_store(&a.Cp[mv_v[k]], mv_c[k]);
     __syncthreads();
     if (threadIdx.x == 0) *mv_n = 0;
 }
@@ -356,7 +375,8 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             w[k] = in ? (ST)a.w[beg + gl + k * G] : (ST)0;
         }
 #pragma unroll
-        for (int k = 0; k < E; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
+        for (int k = 0; k < E; ++k)
+            c[k] = (j[k] >= 0 && j[k] != v) ? live_load<FAST>(&a.Cp[j[k]]) : -1;
         int nonself = 0;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
@@ -374,7 +394,8 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
 #pragma unroll
         for (int k = 0; k < E; ++k) x[k] = own[k] ? (ST)vals[slot[k]] : (ST)0;
 #pragma unroll
-        for (int k = 0; k < E; ++k) sg[k] = (own[k] && c[k] != dc) ? a.Sig[c[k]] : (ST)0;
+        for (int k = 0; k < E; ++k)
+            sg[k] = (own[k] && c[k] != dc) ? live_load<FAST>(&a.Sig[c[k]]) : (ST)0;
         SC best = score_min<SC>();
         int bc = INT_MAX;
         ST hd = 0;
@@ -410,7 +431,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             nonself += __shfl_xor(nonself, o, 64);
         }
         SC gain = 0;
-        const bool mv = has && decide<C>(a, Wv, dc, kv, best, bc, hd, nonself, &gain);
+        const bool mv = has && decide<C, FAST>(a, Wv, dc, kv, best, bc, hd, nonself, &gain);
         if (mv && gl == 0) graph_gain<C>(a, v, gain);
         if (has && gl == 0) {
             ++nv;
@@ -529,7 +550,8 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
 #pragma unroll
             for (int k = 0; k < 4; ++k) w[k] = j[k] >= 0 ? (ST)a.w[beg + e0 + k * BT] : (ST)0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
+            for (int k = 0; k < 4; ++k)
+                c[k] = (j[k] >= 0 && j[k] != v) ? live_load<FAST>(&a.Cp[j[k]]) : -1;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 ne += j[k] >= 0 ? 1 : 0;
@@ -557,14 +579,16 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
+            for (int q = 0; q < 4; ++q)
+                sg[q] = (kk[q] >= 0 && kk[q] != dc) ? live_load<FAST>(&a.Sig[kk[q]]) : (ST)0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) consider<C>(a, Wv, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
         }
         block_reduce<SC, ST, NW>(r, best, bc, hd, nonself);
         if (threadIdx.x == 0) {
             SC gain = 0;
-            const bool mv = decide<C>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0], &gain);
+            const bool mv = decide<C, FAST>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0],
+                                                &gain);
             if (mv) graph_gain<C>(a, v, gain);
             r.move = mv ? 1 : 0;
             ++nv;
@@ -845,7 +869,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
             // a hub row holds more than the LDS row limit of distinct targets, so
             // it always has an entry other than a self-loop
             SC gain = 0;
-            const bool mv = decide<C>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], 1, &gain);
+            const bool mv = decide<C, FAST>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], 1, &gain);
             if (mv) graph_gain<C>(a, v, gain);
             r.move = mv ? 1 : 0;
             ++nv;

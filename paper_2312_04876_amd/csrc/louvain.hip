@@ -155,6 +155,7 @@ enum Fam {
     F_AGGPREP,
     F_FINAL,
     F_COLOUR,
+    F_SEQ,
     F_COUNT
 };
 const char *FAM_NAMES[F_COUNT] = {
@@ -162,13 +163,28 @@ const char *FAM_NAMES[F_COUNT] = {
     "move_bin4_block", "move_bin5_bigblock", "move_bin6_hub", "agg_bin0_4lanes",
     "agg_bin1_4lanes", "agg_bin2_8lanes", "agg_bin3_wave", "agg_bin4_block",
     "agg_bin5_bigblock", "agg_bin6_hub", "compact", "apply", "iteration_end", "level_setup",
-    "aggregate_prep", "final", "colour"};
-static_assert(F_COUNT == 2 * NBINS + 7, "family names");
+    "aggregate_prep", "final", "colour", "move_seq"};
+static_assert(F_COUNT == 2 * NBINS + 8, "family names");
 
 struct Pending {
     int fam;
     hipEvent_t a, b;
+    int pass;  // pass whose phase the launch belongs to
 };
+
+// Phase of a kernel family in the per-pass split of louvain_stats (the split
+// of Section 5.3: local moving, aggregation, other): 0 local moving, 1
+// aggregation (renumbering and the community-vertex CSR included), 2 other
+// (level setup, modularity).
+int phase_of(int fam)
+{
+    if (fam >= F_MOVE0 && fam < F_MOVE0 + NBINS) return 0;
+    if (fam == F_COMPACT || fam == F_APPLY || fam == F_ITER || fam == F_COLOUR || fam == F_SEQ)
+        return 0;
+    if (fam >= F_AGG0 && fam < F_AGG0 + NBINS) return 1;
+    if (fam == F_AGGPREP) return 1;
+    return 2;
+}
 
 thread_local const char *g_last_hip_error = "no HIP error";
 
@@ -353,7 +369,7 @@ int prof_end(louvain_ctx *ctx, int fam, hipEvent_t a)
         ctx->ev_free.pop_back();
     }
     CK(hipEventRecord(b, ctx->s));
-    ctx->pending.push_back(Pending{fam, a, b});
+    ctx->pending.push_back(Pending{fam, a, b, ctx->pass});
     return LOUVAIN_OK;
 }
 
@@ -365,6 +381,14 @@ int prof_collect(louvain_ctx *ctx)
         CK(hipEventElapsedTime(&ms, q.a, q.b));
         ctx->fam_ms[q.fam] += ms;
         ctx->fam_launches[q.fam] += 1;
+        // the modularity after the last pass goes to that pass
+        const int last = ctx->st.passes > 0 ? ctx->st.passes - 1 : 0;
+        const int p = q.pass < last ? q.pass : last;
+        if (p < LOUVAIN_MAX_PASSES) {
+            const int ph = phase_of(q.fam);
+            double *acc = ph == 0 ? ctx->st.ms_move : (ph == 1 ? ctx->st.ms_aggregate : ctx->st.ms_other);
+            acc[p] += ms;
+        }
         ctx->ev_free.push_back(q.a);
         ctx->ev_free.push_back(q.b);
     }
@@ -685,8 +709,38 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
         grid[b] = std::min(g, cap);
         log2s[b] = block_log2s(ctx->bin_maxlen[b]);
     }
+    // fast mode: levels (in a batch: graphs) of at most `small` vertices are moved in
+    // vertex order by one wavefront each; the rounds below handle the rest
+    const int small = ctx->p.small_level == 0 ? SEQ_MAX : (ctx->p.small_level < 0 ? 0 : ctx->p.small_level);
+    bool seq_all = false;
+    if (fast && small > 0 && (ctx->G > 0 || l.n <= small)) {
+        SeqArgs<C> q;
+        q.off = l.off;
+        q.deg = l.deg;
+        q.tgt = l.tgt;
+        q.w = lev_w<C>(l);
+        q.Cp = ctx->Cp;
+        q.K = (const ST *)ctx->K;
+        q.Sig = (ST *)ctx->Sig;
+        q.size = ctx->size;
+        q.act = ctx->fa;  // the flags of iteration 0 (graphs left to the rounds keep theirs)
+        q.n = l.n;
+        q.max_n = small;
+        q.W = ctx->W;
+        q.tau = ctx->tau;
+        q.max_iter = max_it;
+        q.prune = ctx->p.prune;
+        q.sc = ctx->sc;
+        q.bt = a.bt;
+        hipEvent_t ev;
+        TRY(prof_begin(ctx, &ev));
+        launch_seq_level<C>(q, ctx->G > 0 ? ctx->G : 1, s);
+        CKL();
+        TRY(prof_end(ctx, F_SEQ, ev));
+        seq_all = ctx->G == 0;
+    }
     int it;
-    for (it = 0; it < max_it; ++it) {
+    for (it = 0; !seq_all && it < max_it; ++it) {
         uint8_t *cur = (it & 1) ? ctx->fb : ctx->fa;
         uint8_t *nxt = (it & 1) ? ctx->fa : ctx->fb;
         a.flags_next = nxt;
@@ -1130,6 +1184,7 @@ int check_params(const louvain_params *p)
     if (p->hub_rows != 0 && (p->hub_rows < 2048 || p->hub_rows > LDS_MAX_NARROW)) return LOUVAIN_EINVAL;
     if (p->hub_part_pairs != 0 && (p->hub_part_pairs < 1024 || p->hub_part_pairs > hub_part_pairs<int64_t>()))
         return LOUVAIN_EINVAL;
+    if (p->small_level < -1 || p->small_level > SEQ_MAX) return LOUVAIN_EINVAL;
     if (!(p->tolerance_drop > 0.0) || p->aggregation_tolerance != p->aggregation_tolerance ||
         p->tolerance != p->tolerance)
         return LOUVAIN_EINVAL;
@@ -1180,6 +1235,9 @@ void louvain_default_params(louvain_params *p)
     p->seed = 0;
     p->round_bits = 1;
     p->profile = 0;
+    p->hub_rows = 0;
+    p->hub_part_pairs = 0;
+    p->small_level = 0;
 }
 
 int louvain_workspace_size(int32_t n, int64_t nnz, int64_t total_weight, const louvain_params *p,
