@@ -1,10 +1,15 @@
-"""R-MAT scale 24 (2.0e9 entries, total weight past 2^31): parity checks at full size.
+"""R-MAT scale 24 (2.0e9 entries, total weight past 2^31): parity at full size.
 
-Fast mode: a valid partition whose reported modularity is the oracle's modularity of
-that membership, bit for bit.  Deterministic mode: the first synchronous iteration
-(one round, from singletons) checked vertex by vertex on a sample that includes the
-hundred longest rows, each against the oracle on a local replica (tests/replica.py).
+Deterministic mode, pass by pass against the oracle's synchronous run (records written
+by tests/golden/make_golden.py --full rmat24, which calls only the oracle): iterations,
+exact per-iteration gain sums, moves, vertex visits, a digest of the raw labels,
+communities and an order-free digest of the aggregated level graph, then the
+membership digest and Q.  Fast mode: a valid partition whose reported Q is the
+oracle's Q of that membership bit for bit, within 0.01 of the oracle's sequential Q.
 """
+import json
+import os
+import sys
 import time
 
 import numpy as np
@@ -13,56 +18,82 @@ import pytest
 import graphgen
 import oracle
 from gpu_util import is_valid_partition, to_device
-from replica import first_iteration_decision
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+from digest import graph_digest, labels_digest  # noqa: E402
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "reference.json")
 
 
 @pytest.fixture(scope="module")
 def rmat24():
     import torch
     assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    ref = json.load(open(GOLDEN))["rmat24"]
     t0 = time.time()
     print("generating rmat24 ...", flush=True)
     csr = graphgen.workload("rmat24", threads=16)
     print("rmat24: n=%d nnz=%d in %.0f s" % (csr.n, csr.nnz, time.time() - t0), flush=True)
-    g = oracle.as_graph(csr.offsets, csr.targets, csr.weights)
-    K, W = oracle.vertex_weights(g)
-    print("oracle graph and weights ready, W=%d" % W, flush=True)
-    return csr, g, K, W
+    assert (csr.n, csr.nnz, int(csr.weights.sum(dtype=np.int64))) == (ref["n"], ref["nnz"], ref["W"])
+    dev = to_device(csr)
+    iso0 = int((np.diff(csr.offsets) == 0).sum())
+    return csr, dev, ref, iso0
+
+
+def test_rmat24_det_pass_by_pass(rmat24):
+    import paper_2312_04876_amd as P
+    csr, (off, tgt, w), ref, iso0 = rmat24
+    rec = ref["sync"]
+    ctx = P.Louvain(off, tgt, w, mode="deterministic", seed=rec["seed"], round_bits=rec["round_bits"])
+    iso = iso0
+    try:
+        for k, pr in enumerate(rec["per_pass"]):
+            t0 = time.time()
+            it, _ = ctx.move()
+            tr = ctx.move_trace()
+            print("pass %d: %d iterations (%.1f s)" % (k, it, time.time() - t0), flush=True)
+            assert it == pr["iterations"], ("iterations", k)
+            assert [str(x) for x in tr["sumN"]] == pr["sumN"], ("gain sums", k)
+            assert tr["moves"] == pr["moves"], ("moves", k)
+            # isolated vertices are never queued on the GPU; the oracle visits them in the
+            # first iteration
+            assert tr["processed"] == [p - (iso if j == 0 else 0)
+                                       for j, p in enumerate(pr["processed"])], ("processed", k)
+            assert labels_digest(ctx.level_labels().cpu().numpy()) == pr["labels"], ("labels", k)
+            nc, stop = ctx.aggregate()
+            assert nc == pr["communities"], ("communities", k)
+            if "next_level" not in pr:
+                assert stop
+                break
+            t0 = time.time()
+            o, d, t, ww = ctx.level_graph()
+            o, d, t, ww = o.cpu().numpy(), d.cpu().numpy(), t.cpu().numpy(), ww.cpu().numpy()
+            dg = graph_digest(o[:-1], d, t, ww)
+            print("level graph after pass %d: %d vertices, %d entries (%.1f s)" %
+                  (k, dg["n"], dg["entries"], time.time() - t0), flush=True)
+            assert dg == pr["next_level"], ("level graph", k)
+            iso = int((d == 0).sum())
+            del o, d, t, ww
+        memb, q, st = ctx.run()
+        memb = memb.cpu().numpy()
+    finally:
+        ctx.close()
+    print("rmat24 deterministic: Q=%.6f (oracle %.6f)" % (q, rec["Q"]), flush=True)
+    assert labels_digest(memb) == rec["digest"]
+    assert q == rec["Q"]
+    assert st["iterations"] == rec["iterations"] and st["communities"] == rec["communities"]
 
 
 def test_rmat24_fast_full_size(rmat24):
     import paper_2312_04876_amd as P
-    csr, g, K, W = rmat24
-    off, tgt, w = to_device(csr)
+    csr, (off, tgt, w), ref, _ = rmat24
     memb, q, st = P.louvain(off, tgt, w, mode="fast")
     memb = memb.cpu().numpy()
-    del off, tgt, w
-    print("rmat24 fast: Q=%.6f passes=%d" % (q, st["passes"]), flush=True)
+    print("rmat24 fast: Q=%.6f passes=%d, sequential oracle %.6f" % (q, st["passes"],
+                                                                      ref["seq"]["Q"]), flush=True)
     assert is_valid_partition(memb)
+    g = oracle.as_graph(csr.offsets, csr.targets, csr.weights)
     assert q == oracle.modularity(g, memb)
-
-
-def test_rmat24_det_first_iteration_sampled(rmat24):
-    import paper_2312_04876_amd as P
-    csr, g, K, W = rmat24
-    off, tgt, w = to_device(csr)
-    ctx = P.Louvain(off, tgt, w, mode="deterministic", round_bits=0, max_iterations=1,
-                    max_passes=1)
-    try:
-        ctx.move()
-        labels = ctx.level_labels().cpu().numpy()
-    finally:
-        ctx.close()
-    del off, tgt, w
-    deg = np.diff(g.offsets)
-    rng = np.random.default_rng(24)
-    live = np.nonzero(deg > 0)[0]
-    sample = np.unique(np.concatenate((rng.choice(live, size=900, replace=False),
-                                       np.argsort(-deg)[:100])))
-    t0 = time.time()
-    for k, i in enumerate(sample):
-        assert labels[i] == first_iteration_decision(g, K, W, int(i)), int(i)
-        if k % 200 == 0:
-            print("checked %d of %d vertices (%.0f s)" % (k, len(sample), time.time() - t0), flush=True)
+    assert abs(q - ref["seq"]["Q"]) <= 0.01
