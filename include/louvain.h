@@ -308,6 +308,36 @@ int louvain_init_batch(louvain_ctx **ctx, int32_t graphs, const int32_t *graph_o
  */
 int louvain_batch_results(louvain_ctx *ctx, double *modularity, int32_t *communities);
 
+/*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it):
+ * louvain_init + louvain_run + louvain_destroy in one call, with the
+ * library's own device scratch array as the workspace instead of a
+ * caller-provided one.  The array is a file-scope device array of
+ * LOUVAIN_NOALLOC_BYTES (64 MiB) that every GPU the library runs on holds
+ * until the process ends; nothing is allocated on the device or in pinned
+ * host memory, and no events are created (the host waits on the stream
+ * once per local-moving iteration instead of one iteration behind).
+ * Host-side bookkeeping still uses the C++ heap.
+ * Arguments: as louvain_init (offsets, targets, weights: device; p may be
+ * NULL; stream as there) and louvain_run (membership: device int32[n];
+ * modularity: host; stats: host, nullable); the result is the one
+ * louvain_init + louvain_run give on the same input and parameters.
+ * Graphs up to roughly 1.7e6 entries fit: the need is
+ * louvain_workspace_size(n, nnz, -1, p) (sized for 8-byte totals).
+ * Errors: ENOSPC when that need exceeds LOUVAIN_NOALLOC_BYTES; EINVAL for
+ * p->profile = 1 (profiling creates events) and the errors of
+ * louvain_init / louvain_run.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (each call initialises what it reads): calls that overlap on the
+ * same GPU, from several threads or streams, race and must be serialised by
+ * the caller.
+ */
+#define LOUVAIN_NOALLOC_BYTES (64ull << 20)
+int louvain_run_noalloc(int32_t n, int64_t nnz, const int32_t *offsets, const int32_t *targets,
+                        const int32_t *weights, const louvain_params *p, int32_t *membership,
+                        double *modularity, louvain_stats *stats, void *stream);
+
 /* Release host-side state (the caller's device buffers are untouched). NULL is a no-op.
  * The context's pinned host block (a few KB for scalar read-backs) returns to a
  * process-wide pool that later contexts reuse; pinned memory is never freed

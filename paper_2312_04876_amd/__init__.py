@@ -6,8 +6,10 @@ in-tree by ``paper_2312_04876_amd.build``); this package is its Python
 binding.  There is no CPU fallback: without the built library every entry
 point raises.
 """
-from .binding import (DETERMINISTIC, FAST, EXPORTS, Louvain, LouvainError, batch_workspace_bytes,
-                      load_library, louvain, make_params, strerror, workspace_bytes)
+from .binding import (DETERMINISTIC, FAST, EXPORTS, NOALLOC_BYTES, Louvain, LouvainError,
+                      batch_workspace_bytes, load_library, louvain, louvain_noalloc, make_params,
+                      strerror, workspace_bytes)
 
-__all__ = ["DETERMINISTIC", "FAST", "EXPORTS", "Louvain", "LouvainError", "batch_workspace_bytes",
-           "load_library", "louvain", "make_params", "strerror", "workspace_bytes"]
+__all__ = ["DETERMINISTIC", "FAST", "EXPORTS", "NOALLOC_BYTES", "Louvain", "LouvainError",
+           "batch_workspace_bytes", "load_library", "louvain", "louvain_noalloc", "make_params",
+           "strerror", "workspace_bytes"]

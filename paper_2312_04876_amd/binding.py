@@ -30,8 +30,11 @@ EXPORTS = (
     "louvain_level_graph", "louvain_move_trace", "louvain_reset", "louvain_total_weight",
     "louvain_get_stats", "louvain_kernel_stats", "louvain_destroy", "louvain_strerror",
     "louvain_batch_workspace_size", "louvain_init_batch", "louvain_batch_results",
-    "louvain_set_membership",
+    "louvain_set_membership", "louvain_run_noalloc",
 )
+
+# Bytes of the library's own device scratch array (louvain_run_noalloc).
+NOALLOC_BYTES = 64 << 20
 
 
 class CParams(ctypes.Structure):
@@ -137,6 +140,9 @@ def load_library():
     lib.louvain_batch_results.argtypes = [vp, vp, vp]
     lib.louvain_set_membership.restype = ctypes.c_int
     lib.louvain_set_membership.argtypes = [vp, vp]
+    lib.louvain_run_noalloc.restype = ctypes.c_int
+    lib.louvain_run_noalloc.argtypes = [i32, i64, vp, vp, vp, P(CParams), vp, P(dbl), P(CStats),
+                                        vp]
     lib.louvain_destroy.restype = None
     lib.louvain_destroy.argtypes = [vp]
     lib.louvain_strerror.restype = ctypes.c_char_p
@@ -422,3 +428,30 @@ def louvain(offsets, targets, weights, **params):
     finally:
         ctx.close()
 
+
+def louvain_noalloc(offsets, targets, weights, membership, stream=None, **params):
+    """louvain_run_noalloc: the whole method with the library's own device scratch array
+    as the workspace (no device memory allocated here or in the library).  membership:
+    a caller-allocated contiguous int32 CUDA tensor of at least n values.  Returns
+    (Q, per-pass stats dict)."""
+    import torch
+    lib = load_library()
+    for name, t in (("offsets", offsets), ("targets", targets), ("weights", weights),
+                    ("membership", membership)):
+        if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous int32 CUDA tensor" % name)
+    n = int(offsets.numel()) - 1
+    nnz = int(targets.numel())
+    if n < 0 or int(weights.numel()) != nnz or int(membership.numel()) < n:
+        raise ValueError("malformed CSR or membership sizes")
+    prm = make_params(**params)
+    if stream is None:
+        stream = torch.cuda.current_stream(offsets.device)
+    q = ctypes.c_double(0.0)
+    st = CStats()
+    _check(lib.louvain_run_noalloc(n, nnz, offsets.data_ptr(), targets.data_ptr() if nnz else
+                                   offsets.data_ptr(), weights.data_ptr() if nnz else
+                                   offsets.data_ptr(), ctypes.byref(prm), membership.data_ptr(),
+                                   ctypes.byref(q), ctypes.byref(st),
+                                   ctypes.c_void_p(stream.cuda_stream)), "louvain_run_noalloc")
+    return float(q.value), st.as_dict()

@@ -246,6 +246,11 @@ struct louvain_ctx {
     DevScalars *hsc;  // pinned host copy
     int32_t *pinned_done;
     hipEvent_t it_ev[2];
+    // louvain_run_noalloc: read-backs into this pageable memory instead of a
+    // pinned block, and no events (the host waits on the stream each iteration)
+    bool noalloc;
+    DevScalars own_hsc;
+    int32_t own_done[LOUVAIN_MAX_ITERATIONS + 1];
     int32_t *Cp, *top, *size, *binorder, *worklist, *mv_v, *mv_c, *mv_d;
     int32_t *used, *idmap, *ccount, *coff, *ctot, *cursor, *members, *cbinorder;
     uint8_t *fa, *fb;
@@ -867,6 +872,13 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
         TRY(prof_end(ctx, F_ITER, ev));
         CK(hipMemcpyAsync(&ctx->pinned_done[it], &ctx->sc->done, sizeof(int32_t),
                           hipMemcpyDeviceToHost, s));
+        if (ctx->noalloc) {
+            // no events: wait for this iteration (kernels after the done flag are no-ops
+            // anyway, so the result is the same)
+            CK(hipStreamSynchronize(s));
+            if (ctx->pinned_done[it]) break;
+            continue;
+        }
         CK(hipEventRecord(ctx->it_ev[it & 1], s));
         // look one iteration behind so the device always has queued work
         if (it >= 1) {
@@ -1260,7 +1272,8 @@ namespace {
 
 int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t n, int64_t nnz,
              const int32_t *offsets, const int32_t *targets, const int32_t *weights,
-             void *workspace, size_t workspace_bytes, const louvain_params *p, void *stream)
+             void *workspace, size_t workspace_bytes, const louvain_params *p, void *stream,
+             bool noalloc = false)
 {
     if (!out) return LOUVAIN_EINVAL;
     *out = nullptr;
@@ -1298,15 +1311,21 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
         louvain_destroy(ctx);
         return code;
     };
-    PinnedBlock pb;
-    const bool pinned = pinned_take(&pb);
-    ctx->hsc = pb.hsc;
-    ctx->pinned_done = pb.done;
-    if (!pinned ||
-        hipEventCreateWithFlags(&ctx->it_ev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->it_ev[1], hipEventDisableTiming) != hipSuccess) {
-        g_last_hip_error = "host-side allocation failed";
-        return fail(LOUVAIN_EHIP);
+    ctx->noalloc = noalloc;
+    if (noalloc) {
+        ctx->hsc = &ctx->own_hsc;
+        ctx->pinned_done = ctx->own_done;
+    } else {
+        PinnedBlock pb;
+        const bool pinned = pinned_take(&pb);
+        ctx->hsc = pb.hsc;
+        ctx->pinned_done = pb.done;
+        if (!pinned ||
+            hipEventCreateWithFlags(&ctx->it_ev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->it_ev[1], hipEventDisableTiming) != hipSuccess) {
+            g_last_hip_error = "host-side allocation failed";
+            return fail(LOUVAIN_EHIP);
+        }
     }
     // validation and W with the narrow layout's scalar block (same offset in both layouts)
     ctx->L = make_layout(n, nnz, 4, G);
@@ -1693,11 +1712,83 @@ void louvain_destroy(louvain_ctx *ctx)
         hipEventDestroy(q.b);
     }
     for (hipEvent_t e : ctx->ev_free) hipEventDestroy(e);
-    pinned_give(ctx->hsc, ctx->pinned_done);
+    if (!ctx->noalloc) pinned_give(ctx->hsc, ctx->pinned_done);
     for (int k = 0; k < 2; ++k)
         if (ctx->it_ev[k]) hipEventDestroy(ctx->it_ev[k]);
     delete ctx;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- no-allocation entry point
+//
+// The device scratch array of louvain_run_noalloc: one per GPU the library runs
+// on, held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not the device array: its device address comes from
+// hipGetSymbolAddress once per device (noalloc_scratch) and only that address
+// is ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[LOUVAIN_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device), or nullptr on failure.
+void *noalloc_scratch()
+{
+    int dev = -1;
+    const hipError_t ed = hipGetDevice(&dev);
+    if (ed != hipSuccess) {
+        g_last_hip_error = hipGetErrorString(ed);
+        return nullptr;
+    }
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        g_last_hip_error = "device index beyond the scratch-address table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            g_last_hip_error = e != hipSuccess ? hipGetErrorString(e)
+                                               : "hipGetSymbolAddress gave a null address";
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" int louvain_run_noalloc(int32_t n, int64_t nnz, const int32_t *offsets,
+                                   const int32_t *targets, const int32_t *weights,
+                                   const louvain_params *p, int32_t *membership,
+                                   double *modularity, louvain_stats *stats, void *stream)
+{
+    if (p && p->profile) return LOUVAIN_EINVAL;  // profiling creates events
+    size_t need = 0;
+    // sized for 8-byte totals, whatever the weights: the total weight is only known
+    // after validation, and the array must hold either layout
+    const int r = louvain_workspace_size(n, nnz, -1, p, &need);
+    if (r) return r;
+    if (need > (size_t)LOUVAIN_NOALLOC_BYTES) return LOUVAIN_ENOSPC;
+    void *ws = noalloc_scratch();
+    if (!ws) return LOUVAIN_EHIP;
+    louvain_ctx *ctx = nullptr;
+    int rc = init_ctx(&ctx, 0, nullptr, n, nnz, offsets, targets, weights, ws,
+                      (size_t)LOUVAIN_NOALLOC_BYTES, p, stream, true);
+    if (rc) return rc;
+    rc = louvain_run(ctx, membership, modularity, stats);
+    louvain_destroy(ctx);
+    return rc;
+}
+
+extern "C" {
 
 const char *louvain_strerror(int code)
 {

@@ -134,3 +134,33 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "liblouvain.so"))
     with pytest.raises(RuntimeError, match="not built"):
         binding.load_library()
+
+
+def test_noalloc_rejects_sizes_beyond_its_array_before_any_gpu_call(lib):
+    # the size checks come before the device lookup: no pointer is touched
+    import paper_2312_04876_amd as P
+    text = open(HEADER).read()
+    m = re.search(r"#define LOUVAIN_NOALLOC_BYTES \((\d+)ull << (\d+)\)", text)
+    assert m and (int(m.group(1)) << int(m.group(2))) == P.NOALLOC_BYTES
+    q = ctypes.c_double()
+    # a graph whose workspace exceeds the array
+    assert lib.louvain_run_noalloc(1 << 20, 1 << 25, None, None, None, None, None,
+                                   ctypes.byref(q), None, None) == P.binding.ENOSPC
+    # just below and above the limit, by the documented size rule
+    out = ctypes.c_size_t()
+    n = 20000
+    lo, hi = 1, 1 << 24
+    while lo < hi:  # largest nnz that fits
+        mid = (lo + hi + 1) // 2
+        lib.louvain_workspace_size(n, mid, -1, None, ctypes.byref(out))
+        if out.value <= P.NOALLOC_BYTES:
+            lo = mid
+        else:
+            hi = mid - 1
+    assert lib.louvain_run_noalloc(n, lo + 1, None, None, None, None, None, ctypes.byref(q),
+                                   None, None) == P.binding.ENOSPC
+    prof = P.make_params(profile=True)
+    assert lib.louvain_run_noalloc(10, 20, None, None, None, ctypes.byref(prof), None,
+                                   ctypes.byref(q), None, None) == P.binding.EINVAL
+    assert lib.louvain_run_noalloc(-1, 0, None, None, None, None, None, ctypes.byref(q), None,
+                                   None) == P.binding.EINVAL
