@@ -387,8 +387,8 @@ int prof_collect(louvain_ctx *ctx)
         ctx->fam_ms[q.fam] += ms;
         ctx->fam_launches[q.fam] += 1;
         // the modularity after the last pass goes to that pass
-        const int last = ctx->st.passes > 0 ? ctx->st.passes - 1 : 0;
-        const int p = q.pass < last ? q.pass : last;
+        int p = q.pass;
+        if (q.fam == F_FINAL && p >= ctx->st.passes && ctx->st.passes > 0) p = ctx->st.passes - 1;
         if (p < LOUVAIN_MAX_PASSES) {
             const int ph = phase_of(q.fam);
             double *acc = ph == 0 ? ctx->st.ms_move : (ph == 1 ? ctx->st.ms_aggregate : ctx->st.ms_other);
