@@ -104,11 +104,13 @@ typedef struct {
                                      8192, or 4096 when wide) */
     int32_t hub_part_pairs;       /* pairs per hash partition of a hub row in local moving;
                                      1024 .. 2048 (default 2048) */
-    int32_t small_level;          /* LOUVAIN_FAST only: a level (in a batch, a graph's part of
-                                     it) of at most this many vertices is moved in vertex order
-                                     by one wavefront, the asynchronous sweep of Alg. 2 as one
-                                     thread runs it, instead of in concurrent rounds; 1 .. 1024,
-                                     0 = 1024, -1 = never */
+    int32_t small_level;          /* a level (in a batch, a graph's part of it) of at most this
+                                     many vertices is moved by one wavefront, all its iterations
+                                     in one launch: LOUVAIN_FAST in vertex order (the
+                                     asynchronous sweep of Alg. 2 as one thread runs it) instead
+                                     of concurrently, LOUVAIN_DETERMINISTIC in the same
+                                     synchronous rounds (same result); not LOUVAIN_COLOURED;
+                                     1 .. 1024, 0 = 1024, -1 = never */
 } louvain_params;
 
 /* Per-pass record of the last louvain_run / louvain_move / louvain_aggregate sequence. */

@@ -222,9 +222,10 @@ template <class C>
 void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int32_t parts,
                       int grid, int64_t *scratch, hipStream_t s);
 
-// Fast mode on small levels: one wavefront per graph (one in total for a
-// single graph) runs the whole local-moving phase of a level of at most max_n
-// vertices in vertex order (Alg. 2 as one thread executes it), then marks the
+// Small levels: one wavefront per graph (one in total for a single graph)
+// runs the whole local-moving phase of a level of at most max_n vertices, in
+// vertex order (fast mode: Alg. 2 as one thread executes it) or in the
+// synchronous rounds of the degree bins (deterministic mode), then marks the
 // graph converged for the pass; larger graphs are left to the degree bins.
 template <class C>
 struct SeqArgs {
@@ -234,18 +235,23 @@ struct SeqArgs {
     const typename C::ST *K;
     typename C::ST *Sig;
     int32_t *size;
-    uint8_t *act;        // active flags of the level (one array, marked within the sweep)
+    uint8_t *act;        // active flags of the level
+    uint8_t *mark;       // deterministic mode: rows of this iteration's movers
+    int32_t *mv_v, *mv_c;  // deterministic mode: a round's moves (each graph in its range)
     int32_t n;           // vertices of the level (a single graph)
     int32_t max_n;       // largest graph moved here (at most SEQ_MAX)
     int64_t W;           // total weight (a single graph; a batch uses bt.gW)
     double tau;
     int32_t max_iter, prune;
+    int32_t rule;        // deterministic mode: min-label rule for singleton moves
+    uint64_t seed;       // deterministic mode: round hash of (seed, pass, iteration, vertex)
+    int32_t round_bits, pass;
     DevScalars *sc;      // a single graph: per-iteration trace, iterations, done
     BatchArgs bt;
 };
 // grid: graphs (1 for a single graph).
 template <class C>
-void launch_seq_level(const SeqArgs<C> &a, int graphs, hipStream_t s);
+void launch_seq_level(const SeqArgs<C> &a, bool fast, int graphs, hipStream_t s);
 
 // Deferred moves of a round (deterministic mode): each mover relabelled, and
 // the community weights and sizes updated, each workgroup combining the

@@ -714,11 +714,12 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
         grid[b] = std::min(g, cap);
         log2s[b] = block_log2s(ctx->bin_maxlen[b]);
     }
-    // fast mode: levels (in a batch: graphs) of at most `small` vertices are moved in
-    // vertex order by one wavefront each; the rounds below handle the rest
+    // levels (in a batch: graphs) of at most `small` vertices are moved by one
+    // wavefront each, every iteration in one launch (fast mode: in vertex order;
+    // deterministic mode: in the same synchronous rounds); the bins below handle the rest
     const int small = ctx->p.small_level == 0 ? SEQ_MAX : (ctx->p.small_level < 0 ? 0 : ctx->p.small_level);
     bool seq_all = false;
-    if (fast && small > 0 && (ctx->G > 0 || l.n <= small)) {
+    if (!coloured && small > 0 && (ctx->G > 0 || (l.n >= 1 && l.n <= small))) {
         SeqArgs<C> q;
         q.off = l.off;
         q.deg = l.deg;
@@ -729,6 +730,13 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
         q.Sig = (ST *)ctx->Sig;
         q.size = ctx->size;
         q.act = ctx->fa;  // the flags of iteration 0 (graphs left to the rounds keep theirs)
+        q.mark = ctx->fb;
+        q.mv_v = ctx->mv_v;
+        q.mv_c = ctx->mv_c;
+        q.rule = 1;
+        q.seed = ctx->p.seed;
+        q.round_bits = ctx->p.round_bits;
+        q.pass = ctx->pass;
         q.n = l.n;
         q.max_n = small;
         q.W = ctx->W;
@@ -739,7 +747,7 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
         q.bt = a.bt;
         hipEvent_t ev;
         TRY(prof_begin(ctx, &ev));
-        launch_seq_level<C>(q, ctx->G > 0 ? ctx->G : 1, s);
+        launch_seq_level<C>(q, fast, ctx->G > 0 ? ctx->G : 1, s);
         CKL();
         TRY(prof_end(ctx, F_SEQ, ev));
         seq_all = ctx->G == 0;

@@ -62,16 +62,20 @@ def alone(csr, **params):
     return memb.cpu().numpy()[:csr.n], q
 
 
-@pytest.mark.parametrize("round_bits", [1, 0, 2])
-def test_batch_det_equals_each_graph_alone(round_bits):
+@pytest.mark.parametrize("round_bits,small_level", [(1, 0), (0, 0), (2, 0), (1, -1), (1, 256)])
+def test_batch_det_equals_each_graph_alone(round_bits, small_level):
+    # small_level 0: graphs (and coarse levels) of at most 1024 vertices are moved by one
+    # wavefront each; -1: everything in the degree bins' rounds; 256: a mix
     graphs = mixed_graphs()
-    parts, qs, comms = run_batch(graphs, mode="deterministic", round_bits=round_bits)
+    parts, qs, comms = run_batch(graphs, mode="deterministic", round_bits=round_bits,
+                                 small_level=small_level)
     for g, csr in enumerate(graphs):
-        m1, q1 = alone(csr, mode="deterministic", round_bits=round_bits)
+        m1, q1 = alone(csr, mode="deterministic", round_bits=round_bits, small_level=small_level)
         assert np.array_equal(parts[g], m1), csr.name
         assert qs[g] == q1, csr.name
         assert comms[g] == (len(np.unique(m1)) if csr.n else 0), csr.name
-        assert qs[g] == oracle.modularity(_og(csr), parts[g]), csr.name
+        mo, qo, _ = oracle.louvain(_og(csr), oracle.Params(mode="sync", sample_bits=round_bits))
+        assert np.array_equal(parts[g], mo) and qs[g] == qo, csr.name
 
 
 def test_batch_coloured_equals_each_graph_alone_and_the_oracle():

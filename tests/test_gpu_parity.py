@@ -110,9 +110,12 @@ def small_graphs():
         yield graphgen.from_edges(n, e, w, name="rand%d" % n)
 
 
+@pytest.mark.parametrize("small_level", [0, -1])
 @pytest.mark.parametrize("idx", range(6))
-def test_det_small(idx):
-    det_parity(list(small_graphs())[idx])
+def test_det_small(idx, small_level):
+    # small_level 0: these levels are moved by one wavefront each (k_sync_level);
+    # -1: by the degree bins' rounds
+    det_parity(list(small_graphs())[idx], small_level=small_level)
 
 
 @pytest.mark.parametrize("wl", ["sbm10k", "rmat12-8", "rmat14-16", "rmat16-16"])
@@ -226,6 +229,7 @@ def test_det_and_coloured_random_graphs(seed):
     w += [int(x) for x in rng.integers(1, 10, size=min(n, 40 + 120 * seed) - 1)]
     csr = graphgen.from_edges(n, e, w, name="rand%d" % seed)
     det_parity(csr, round_bits=seed % 3, seed=seed)
+    det_parity(csr, round_bits=seed % 3, seed=seed, small_level=-1)
     det_parity(csr, coloured=True, seed=seed)
     # fast mode: a valid partition whose reported Q is the oracle's Q of it, bit for bit,
     # no more than 0.01 below the sequential oracle over its own vertex order and eight
