@@ -347,9 +347,11 @@ def batch_main(args):
         from paper_2312_04876_amd import autotune
         tuned = autotune.tune(off, tgt, w, graph_offsets=go, runs=2, warmup=1, **opts)
         uopts.update(autotune.tuned_params(tuned))
-        print("autotune (union): hub_rows %d, hub_part_pairs %d (%.1f s)" %
-              (tuned["hub_rows"], tuned["hub_part_pairs"], tuned["seconds"]), file=sys.stderr,
-              flush=True)
+        print("autotune (union): hub_rows %d, hub_part_pairs %d, small_level %d (%.1f s; %s)" %
+              (tuned["hub_rows"], tuned["hub_part_pairs"], tuned["small_level"], tuned["seconds"],
+               ", ".join("%d/%d/%d %.1f ms" % (r["hub_rows"], r["hub_part_pairs"],
+                                               r["small_level"], r["ms"]) for r in tuned["table"])),
+              file=sys.stderr, flush=True)
     ctx = P.Louvain(off, tgt, w, graph_offsets=go, **uopts)
     run_steps(ctx, memb, args.warmup)
     sec_b, (m, _q, st) = run_steps(ctx, memb, args.steps)
@@ -654,9 +656,10 @@ def measure(args, csr, name, steps, warmup):
         from paper_2312_04876_amd import autotune
         tuned = autotune.tune(off, tgt, w, runs=2, warmup=1, **opts)
         opts.update(autotune.tuned_params(tuned))
-        print("autotune: hub_rows %d, hub_part_pairs %d (%.1f s; %s)" %
-              (tuned["hub_rows"], tuned["hub_part_pairs"], tuned["seconds"],
-               ", ".join("%d/%d %.2f ms" % (r["hub_rows"], r["hub_part_pairs"], r["ms"])
+        print("autotune: hub_rows %d, hub_part_pairs %d, small_level %d (%.1f s; %s)" %
+              (tuned["hub_rows"], tuned["hub_part_pairs"], tuned["small_level"], tuned["seconds"],
+               ", ".join("%d/%d/%d %.2f ms" % (r["hub_rows"], r["hub_part_pairs"],
+                                               r["small_level"], r["ms"])
                          for r in tuned["table"])), file=sys.stderr, flush=True)
 
     # timed region 1: the plain path

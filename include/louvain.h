@@ -110,7 +110,8 @@ typedef struct {
                                      asynchronous sweep of Alg. 2 as one thread runs it) instead
                                      of concurrently, LOUVAIN_DETERMINISTIC in the same
                                      synchronous rounds (same result); not LOUVAIN_COLOURED;
-                                     1 .. 1024, 0 = 1024, -1 = never */
+                                     1 .. 1024, -1 = never, 0 = the default: 1024 in
+                                     LOUVAIN_FAST, never in LOUVAIN_DETERMINISTIC */
 } louvain_params;
 
 /* Per-pass record of the last louvain_run / louvain_move / louvain_aggregate sequence. */

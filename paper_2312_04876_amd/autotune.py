@@ -1,12 +1,15 @@
 """Autotuner for the scheduling knobs of the library.
 
-Two knobs decide how rows are scheduled, never what is computed (deterministic
-runs are bit-identical under every setting):
+Three knobs decide how rows are scheduled (deterministic runs are
+bit-identical under every setting):
 
 * ``hub_rows``: rows (and, in aggregation, communities) longer than this take
   the hub path, whose rows are counting-sorted into hash partitions, instead of
   one 512-thread workgroup with an LDS table;
-* ``hub_part_pairs``: pairs per hash partition of a hub row in local moving.
+* ``hub_part_pairs``: pairs per hash partition of a hub row in local moving;
+* ``small_level``: a level (in a batch, a graph's part of it) of at most this
+  many vertices is moved by one wavefront in one launch instead of by the
+  degree bins' rounds (in fast mode this also means in vertex order).
 
 :func:`tune` times every candidate setting on the caller's own graph (or batch
 union) with inputs resident on the GPU and returns the fastest, so a workload
@@ -24,6 +27,7 @@ from .binding import Louvain
 
 HUB_ROWS = (2048, 4096, 8192)
 HUB_PART_PAIRS = (1024, 2048)
+SMALL_LEVELS = (-1, 256, 1024)
 WIDE_LDS_ROWS = 4096  # the hub threshold is clamped to this with 8-byte accumulators
 
 
@@ -52,8 +56,9 @@ def candidates(wide: bool) -> List[Tuple[int, int]]:
 def tune(offsets, targets, weights, graph_offsets=None, runs: int = 2, warmup: int = 1,
          cache_path: Optional[str] = None, stream=None, **params) -> Dict:
     """Time every candidate (hub_rows, hub_part_pairs) over `runs` whole runs after
-    `warmup` untimed ones; returns {"hub_rows", "hub_part_pairs", "ms", "table",
-    "seconds", "signature", "cached"}.  `params` are the run's other parameters."""
+    `warmup` untimed ones, then every small_level with the best of them; returns
+    {"hub_rows", "hub_part_pairs", "small_level", "ms", "table", "seconds",
+    "signature", "cached"}.  `params` are the run's other parameters."""
     import torch
     key = signature(offsets, weights, graph_offsets, **params)
     cache: Dict = {}
@@ -69,9 +74,10 @@ def tune(offsets, targets, weights, graph_offsets=None, runs: int = 2, warmup: i
     table = []
     n = int(offsets.numel()) - 1
     memb = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device)
-    for rows, pairs in candidates(wide):
+
+    def timed(rows, pairs, small):
         ctx = Louvain(offsets, targets, weights, stream=stream, graph_offsets=graph_offsets,
-                      hub_rows=rows, hub_part_pairs=pairs, **params)
+                      hub_rows=rows, hub_part_pairs=pairs, small_level=small, **params)
         try:
             for _ in range(warmup):
                 ctx.reset()
@@ -86,11 +92,21 @@ def tune(offsets, targets, weights, graph_offsets=None, runs: int = 2, warmup: i
                 times.append(time.perf_counter() - t0)
         finally:
             ctx.close()
-        table.append({"hub_rows": rows, "hub_part_pairs": pairs, "ms": min(times) * 1e3})
+        table.append({"hub_rows": rows, "hub_part_pairs": pairs, "small_level": small,
+                      "ms": min(times) * 1e3})
+
+    for rows, pairs in candidates(wide):
+        timed(rows, pairs, 0)
+    best = min(table, key=lambda r: r["ms"])
+    # the built-in small_level (0) is 1024 in fast mode and none (-1) in deterministic mode
+    builtin = 1024 if params.get("mode") == "fast" else -1
+    for small in SMALL_LEVELS:
+        if small != builtin:
+            timed(best["hub_rows"], best["hub_part_pairs"], small)
     best = min(table, key=lambda r: r["ms"])
     out = {"hub_rows": best["hub_rows"], "hub_part_pairs": best["hub_part_pairs"],
-           "ms": best["ms"], "table": table, "seconds": time.perf_counter() - t_start,
-           "signature": key, "cached": False}
+           "small_level": best["small_level"] or builtin, "ms": best["ms"], "table": table,
+           "seconds": time.perf_counter() - t_start, "signature": key, "cached": False}
     if cache_path:
         cache[key] = out
         tmp = cache_path + ".tmp"
@@ -101,4 +117,5 @@ def tune(offsets, targets, weights, graph_offsets=None, runs: int = 2, warmup: i
 
 
 def tuned_params(result: Dict) -> Dict[str, int]:
-    return {"hub_rows": int(result["hub_rows"]), "hub_part_pairs": int(result["hub_part_pairs"])}
+    return {"hub_rows": int(result["hub_rows"]), "hub_part_pairs": int(result["hub_part_pairs"]),
+            "small_level": int(result.get("small_level", 0))}

@@ -182,7 +182,8 @@ struct BatchArgs {
     const int32_t *gvb;        // first vertex of each graph at this level (G + 1)
     const int64_t *gW;         // total weight (2m) per graph
     unsigned long long *gsum;  // 128-bit gain sum per graph, this iteration
-    int32_t *gst;              // bit 0: converged in this pass, bit 1: stopped
+    int32_t *gst;              // bit 0: converged in this pass, bit 1: stopped,
+                               // bit 2: moved by a wavefront of its own in this pass
     int32_t *giter;            // iterations run in this pass
     int32_t G;
 };

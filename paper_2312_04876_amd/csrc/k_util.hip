@@ -753,6 +753,17 @@ __global__ void k_batch_pass_begin(BatchArgs b)
     }
 }
 
+// Graphs of at most max_n vertices (not stopped) are moved by a wavefront of
+// their own in this pass (bit 2); the degree bins skip them from now on.
+__global__ void k_batch_mark_small(BatchArgs b, int32_t max_n)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < b.G; g += gridDim.x * blockDim.x) {
+        if (b.gst[g] & 2) continue;
+        const int nv = b.gvb[g + 1] - b.gvb[g];
+        if (nv >= 1 && nv <= max_n) b.gst[g] |= 4;
+    }
+}
+
 // End of an iteration, per graph still moving: one more iteration, then its
 // own delta-Q test; counts the graphs that keep moving in sc->running.
 __global__ void k_batch_iter_end(BatchArgs b, DevScalars *sc, double tau)
@@ -1168,6 +1179,11 @@ void launch_batch_check(int32_t n, const int32_t *off, const int32_t *tgt, const
 void launch_batch_reset(const BatchArgs &b, int32_t *gcomm, hipStream_t s)
 {
     if (b.G > 0) k_batch_reset<<<grid_for(b.G, 256), 256, 0, s>>>(b, gcomm);
+}
+
+void launch_batch_mark_small(const BatchArgs &b, int32_t max_n, hipStream_t s)
+{
+    if (b.G > 0) k_batch_mark_small<<<grid_for(b.G, 256), 256, 0, s>>>(b, max_n);
 }
 
 void launch_batch_pass_begin(const BatchArgs &b, hipStream_t s)

@@ -290,6 +290,9 @@ void launch_batch_check(int32_t n, const int32_t *off, const int32_t *tgt, const
 void launch_batch_reset(const BatchArgs &b, int32_t *gcomm, hipStream_t s);
 // Start of a local-moving phase: converged bits, iteration counts and gain sums cleared.
 void launch_batch_pass_begin(const BatchArgs &b, hipStream_t s);
+// Marks the graphs of at most max_n vertices (not stopped) for the small-level
+// kernels of this pass (gst bit 2), which the degree bins then skip.
+void launch_batch_mark_small(const BatchArgs &b, int32_t max_n, hipStream_t s);
 // Per-graph community bases (gvb_next), counts (gcomm) and stop test; sc->alive (zero on
 // entry) counts the graphs that go on.
 void launch_batch_agg_test(const BatchArgs &b, const int32_t *idmap, int32_t n, int32_t nc,

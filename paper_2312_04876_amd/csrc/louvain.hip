@@ -237,6 +237,10 @@ void pinned_give(DevScalars *hsc, int32_t *done)
 struct louvain_ctx {
     louvain_params p;
     hipStream_t s;
+    // batches: a second stream on which the small graphs' wavefront kernel runs beside
+    // the degree bins of the others, with the events that fork and join it
+    hipStream_t s2;
+    hipEvent_t fork_ev, join_ev;
     int32_t n;
     int64_t nnz;
     const int32_t *in_off, *in_tgt, *in_w;
@@ -717,8 +721,12 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
     // levels (in a batch: graphs) of at most `small` vertices are moved by one
     // wavefront each, every iteration in one launch (fast mode: in vertex order;
     // deterministic mode: in the same synchronous rounds); the bins below handle the rest
-    const int small = ctx->p.small_level == 0 ? SEQ_MAX : (ctx->p.small_level < 0 ? 0 : ctx->p.small_level);
+    // (default: fast mode SEQ_MAX, for its quality; deterministic mode none, whose
+    // result is the same either way and whose bins are faster on the measured batches)
+    const int small = ctx->p.small_level == 0 ? (fast ? SEQ_MAX : 0)
+                                              : (ctx->p.small_level < 0 ? 0 : ctx->p.small_level);
     bool seq_all = false;
+    bool seq_joined = true;
     if (!coloured && small > 0 && (ctx->G > 0 || (l.n >= 1 && l.n <= small))) {
         SeqArgs<C> q;
         q.off = l.off;
@@ -745,12 +753,30 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
         q.prune = ctx->p.prune;
         q.sc = ctx->sc;
         q.bt = a.bt;
-        hipEvent_t ev;
-        TRY(prof_begin(ctx, &ev));
-        launch_seq_level<C>(q, fast, ctx->G > 0 ? ctx->G : 1, s);
-        CKL();
-        TRY(prof_end(ctx, F_SEQ, ev));
-        seq_all = ctx->G == 0;
+        if (ctx->G == 0) {
+            hipEvent_t ev;
+            TRY(prof_begin(ctx, &ev));
+            launch_seq_level<C>(q, fast, 1, s);
+            CKL();
+            TRY(prof_end(ctx, F_SEQ, ev));
+            seq_all = true;
+        } else {
+            launch_batch_mark_small(a.bt, small, s);
+            CKL();
+            if (ctx->s2) {
+                // the small graphs on the second stream, beside the bins of the others
+                // (disjoint vertex ranges); joined before the phase ends
+                CK(hipEventRecord(ctx->fork_ev, s));
+                CK(hipStreamWaitEvent(ctx->s2, ctx->fork_ev, 0));
+                launch_seq_level<C>(q, fast, ctx->G, ctx->s2);
+                CKL();
+                CK(hipEventRecord(ctx->join_ev, ctx->s2));
+                seq_joined = false;
+            } else {
+                launch_seq_level<C>(q, fast, ctx->G, s);
+                CKL();
+            }
+        }
     }
     int it;
     for (it = 0; !seq_all && it < max_it; ++it) {
@@ -894,6 +920,7 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
             if (ctx->pinned_done[it - 1]) break;
         }
     }
+    if (!seq_joined) CK(hipStreamWaitEvent(s, ctx->join_ev, 0));
     TRY(read_scalars(ctx));
     const DevScalars &h = *ctx->hsc;
     ctx->iters_last = h.iters;
@@ -1453,6 +1480,13 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
             return fail(LOUVAIN_EHIP);
         }
         if (ctx->hsc->err) return fail(LOUVAIN_EINVAL);
+        if (!noalloc &&
+            (hipStreamCreateWithFlags(&ctx->s2, hipStreamNonBlocking) != hipSuccess ||
+             hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess)) {
+            g_last_hip_error = "creating the second stream failed";
+            return fail(LOUVAIN_EHIP);
+        }
     }
     launch_iota(ctx->top, n, ctx->s);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->s) != hipSuccess) {
@@ -1723,6 +1757,12 @@ void louvain_destroy(louvain_ctx *ctx)
     if (!ctx->noalloc) pinned_give(ctx->hsc, ctx->pinned_done);
     for (int k = 0; k < 2; ++k)
         if (ctx->it_ev[k]) hipEventDestroy(ctx->it_ev[k]);
+    if (ctx->s2) {
+        (void)hipStreamSynchronize(ctx->s2);
+        hipStreamDestroy(ctx->s2);
+    }
+    if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) hipEventDestroy(ctx->join_ev);
     delete ctx;
 }
 

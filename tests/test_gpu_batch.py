@@ -62,10 +62,12 @@ def alone(csr, **params):
     return memb.cpu().numpy()[:csr.n], q
 
 
-@pytest.mark.parametrize("round_bits,small_level", [(1, 0), (0, 0), (2, 0), (1, -1), (1, 256)])
+@pytest.mark.parametrize("round_bits,small_level", [(1, 1024), (0, 1024), (2, 1024), (1, 0),
+                                                     (1, 256)])
 def test_batch_det_equals_each_graph_alone(round_bits, small_level):
-    # small_level 0: graphs (and coarse levels) of at most 1024 vertices are moved by one
-    # wavefront each; -1: everything in the degree bins' rounds; 256: a mix
+    # small_level 1024: graphs (and coarse levels) of at most 1024 vertices are moved by one
+    # wavefront each; 0 (the deterministic default): everything in the degree bins' rounds;
+    # 256: a mix
     graphs = mixed_graphs()
     parts, qs, comms = run_batch(graphs, mode="deterministic", round_bits=round_bits,
                                  small_level=small_level)

@@ -110,11 +110,11 @@ def small_graphs():
         yield graphgen.from_edges(n, e, w, name="rand%d" % n)
 
 
-@pytest.mark.parametrize("small_level", [0, -1])
+@pytest.mark.parametrize("small_level", [1024, 0])
 @pytest.mark.parametrize("idx", range(6))
 def test_det_small(idx, small_level):
-    # small_level 0: these levels are moved by one wavefront each (k_sync_level);
-    # -1: by the degree bins' rounds
+    # small_level 1024: these levels are moved by one wavefront each (k_sync_level);
+    # 0 (the deterministic default): by the degree bins' rounds
     det_parity(list(small_graphs())[idx], small_level=small_level)
 
 
@@ -229,7 +229,7 @@ def test_det_and_coloured_random_graphs(seed):
     w += [int(x) for x in rng.integers(1, 10, size=min(n, 40 + 120 * seed) - 1)]
     csr = graphgen.from_edges(n, e, w, name="rand%d" % seed)
     det_parity(csr, round_bits=seed % 3, seed=seed)
-    det_parity(csr, round_bits=seed % 3, seed=seed, small_level=-1)
+    det_parity(csr, round_bits=seed % 3, seed=seed, small_level=1024)
     det_parity(csr, coloured=True, seed=seed)
     # fast mode: a valid partition whose reported Q is the oracle's Q of it, bit for bit,
     # no more than 0.01 below the sequential oracle over its own vertex order and eight
@@ -565,6 +565,7 @@ def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
     res = autotune.tune(off, tgt, w, runs=1, warmup=1, cache_path=cache, mode="fast")
     print("autotune", res["hub_rows"], res["hub_part_pairs"], res["table"], flush=True)
     assert (res["hub_rows"], res["hub_part_pairs"]) in autotune.candidates(wide=False)
-    assert len(res["table"]) == 6 and not res["cached"]
+    assert res["small_level"] in (-1, 256, 1024)
+    assert len(res["table"]) == 6 + 2 and not res["cached"]
     again = autotune.tune(off, tgt, w, cache_path=cache, mode="fast")
     assert again["cached"] and again["hub_rows"] == res["hub_rows"]
