@@ -93,7 +93,8 @@ FAMILY_KERNELS = {
     "move_bin3_wave": [r"k_move_wave<[^>]*>, 64, 8, 10,"],
     "move_bin4_block": [r"k_move_block<[^>]*>, 256,"],
     "move_bin5_bigblock": [r"k_move_block<[^>]*>, 512,"],
-    "move_bin6_hub": [r"k_move_hub<", r"k_hub_count<", r"k_hub_fill<", r"k_hub_part<"],
+    "move_bin6_hub": [r"k_move_hub<", r"k_hub_count<", r"k_hub_fill<", r"k_hub_part<",
+                      r"k_hub_mark<"],
     "move_seq": [r"k_seq_level<"],
     "agg_bin0_4lanes": [r"k_agg_wave<[^>]*>, 4, 4>"],
     "agg_bin1_4lanes": [r"k_agg_wave<[^>]*>, 4, 6>"],

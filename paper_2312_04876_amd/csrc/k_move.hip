@@ -843,8 +843,6 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
         const int p = a.worklist[a.list_begin + idx];
         const int h = p - a.list_begin;
         const int v = a.binorder[p];
-        const int beg = a.off[v];
-        const int d = row_len(a.off, a.deg, v);
         const int q1 = h + 1 < a.nhubs ? a.htslice[h + 1] : (int)*a.htslices;
         const int dc = a.Cp[v];
         const ST kv = a.K[v];
@@ -864,27 +862,37 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
         }
         block_reduce<SC, ST, NW>(r, best, bc, hd, keys);
         if (threadIdx.x == 0) {
-            a.hub_act[h] = 0;
             nk += (unsigned long long)r.nonself[0];
             // a hub row holds more than the LDS row limit of distinct targets, so
             // it always has an entry other than a self-loop
             SC gain = 0;
             const bool mv = decide<C, FAST>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], 1, &gain);
             if (mv) graph_gain<C>(a, v, gain);
-            r.move = mv ? 1 : 0;
             ++nv;
             if (mv) {
                 gain_acc += gain;
                 ++nm;
                 record_move<C, FAST>(a, v, dc, r.bc[0], kv);
             }
+            // k_hub_mark marks the rows of the movers (2) over their sorting slices
+            a.hub_act[h] = mv ? 2 : 0;
         }
-        __syncthreads();
-        if (r.move)
-            for (int e = threadIdx.x; e < d; e += HUB_THREADS) a.flags_next[a.tgt[beg + e]] = 1;
         __syncthreads();
     }
     flush_counters<C>(a, gain_acc, nv, 0, nk, nm);
+}
+
+// Hubs, step 5: one workgroup per sorting slice of a hub that moved marks the
+// slice's entries active for the next iteration (pruning), so a giant row is
+// marked by many workgroups instead of the one that decided it.
+template <class C>
+__global__ __launch_bounds__(256) void k_hub_mark(MoveArgs<C> a)
+{
+    if (*a.done) return;
+    int h, v, beg, e0, e1, parts, gp0;
+    if (!hub_slice(a, (int)blockIdx.x + a.slice_base, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
+    if (a.hub_act[h] != 2) return;
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) a.flags_next[a.tgt[beg + e]] = 1;
 }
 
 template <class C, int BT, bool FAST>
@@ -973,6 +981,8 @@ void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int3
         k_move_hub<C, true><<<grid, HUB_THREADS, 0, s>>>(a);
     else
         k_move_hub<C, false><<<grid, HUB_THREADS, 0, s>>>(a);
+    k_hub_mark<C><<<sort_slices, 256, 0, s>>>(a);
+    launch_fill_u8(a.hub_act, 0, a.nhubs, s);  // every hub inactive again for the next round
 }
 template void launch_move_hubs<CfgNarrow>(bool, const MoveArgs<CfgNarrow> &, int32_t, int32_t,
                                           int, int64_t *, hipStream_t);

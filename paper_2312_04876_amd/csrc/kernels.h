@@ -199,7 +199,7 @@ struct MoveArgs {
     int32_t *pk;                       // partitioned pairs (community, weight)
     typename C::ST *pw;
     void *hpart;                       // HubPart<C> per partition
-    uint8_t *hub_act;                  // hub queued in this round
+    uint8_t *hub_act;                  // hub queued in this round (2 once it has moved)
     int32_t nhubs;
     unsigned long long *spread;        // NSPREAD counter rows of SPREAD_W words
     int32_t bin;                       // degree bin of this launch (counter columns)
