@@ -85,16 +85,18 @@ __device__ inline void live_store(int32_t *p, int32_t v)
 }
 
 // Decision for vertex v once the group knows (best score, its community,
-// weight to the own community, non-self entries).  Returns true to move and
-// sets the gain N = best - stay.
+// weight to the own community, non-self entries).  sd is the own community's
+// total as the caller read it; fast mode reads the live total again here.
+// Returns true to move and sets the gain N = best - stay.
 template <class C, bool FAST>
 __device__ inline bool decide(const MoveArgs<C> &a, int64_t W, int dc, typename C::ST kv,
                               typename C::SC best, int bc, typename C::ST hd, int nonself,
-                              typename C::SC *gain)
+                              typename C::ST sd, typename C::SC *gain)
 {
     typedef typename C::SC SC;
     if (nonself <= 0 || bc == INT_MAX) return false;
-    const SC stay = (SC)W * (SC)hd - (SC)kv * ((SC)live_load<FAST>(&a.Sig[dc]) - (SC)kv);
+    if (FAST) sd = live_load<FAST>(&a.Sig[dc]);
+    const SC stay = (SC)W * (SC)hd - (SC)kv * ((SC)sd - (SC)kv);
     if (!(best > stay)) return false;
     if (a.rule && live_load<FAST>(&a.size[dc]) == 1 && live_load<FAST>(&a.size[bc]) == 1 &&
         bc > dc)
@@ -271,6 +273,48 @@ __device__ inline void consider(const MoveArgs<C> &a, int64_t W, int dc, typenam
     }
 }
 
+// Score bound (Eq. 2 in the integer form of `consider`).  A community total is
+// a sum of non-negative vertex weights, so a candidate's score W*x - K_i*Sigma_c
+// never exceeds W*x.  A candidate with W*x <= stay therefore cannot make a
+// move, and one with W*x below a score already found cannot be or tie the
+// best; neither needs its total read.  Reading the totals of the candidates
+// whose bound reaches the floor (stay + 1, raised to the best score of a first
+// round over the heaviest candidates) leaves every decision as it was: the
+// best candidate and every candidate tying it are read, and when the best
+// does not beat staying no move happens either way.
+template <class C>
+__device__ inline bool worth_reading(int64_t W, typename C::ST x, typename C::SC floor)
+{
+    typedef typename C::SC SC;
+    return (SC)W * (SC)x >= floor;
+}
+
+// The floor of the candidates' scores: one above the score of staying.
+template <class C>
+__device__ inline typename C::SC score_floor(int64_t W, typename C::ST hd, typename C::ST kv,
+                                             typename C::ST sd)
+{
+    typedef typename C::SC SC;
+    return (SC)W * (SC)hd - (SC)kv * ((SC)sd - (SC)kv) + 1;
+}
+
+// Maximum over a workgroup of NW wavefronts, returned to every thread; buf
+// holds NW values in LDS.  Every thread of the workgroup calls this.
+template <typename T, int NW>
+__device__ inline T block_max(T v, T *buf)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const T ov = shfl_xor_t<T>(v, o);
+        v = ov > v ? ov : v;
+    }
+    if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T m = buf[0];
+    for (int k = 1; k < NW; ++k) m = buf[k] > m ? buf[k] : m;
+    __syncthreads();
+    return m;
+}
+
 // Insert (c, w) into a power-of-two LDS table; returns the slot, and sets
 // *own when this call created the key.
 template <typename ST>
@@ -356,7 +400,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
         const bool has = idx < count;
         const int v = has ? a.worklist[a.list_begin + idx] : 0;
         int beg = 0, d = 0, dc = -1;
-        ST kv = 0;
+        ST kv = 0, sd = 0;
         int64_t Wv = a.W;
         if (has) {
             beg = a.off[v];
@@ -374,6 +418,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             j[k] = in ? a.tgt[beg + gl + k * G] : -1;
             w[k] = in ? (ST)a.w[beg + gl + k * G] : (ST)0;
         }
+        if (has) sd = live_load<FAST>(&a.Sig[dc]);
 #pragma unroll
         for (int k = 0; k < E; ++k)
             c[k] = (j[k] >= 0 && j[k] != v) ? live_load<FAST>(&a.Cp[j[k]]) : -1;
@@ -386,31 +431,17 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
             if (c[k] >= 0) {
                 ++nonself;
                 slot[k] = lds_insert_slot<VT>(keys, vals, LOG2S, c[k], (VT)w[k], &own[k]);
-                nk += own[k] ? 1 : 0;
             }
         }
         wave_sync();
-        ST x[E], sg[E];
-#pragma unroll
-        for (int k = 0; k < E; ++k) x[k] = own[k] ? (ST)vals[slot[k]] : (ST)0;
-#pragma unroll
-        for (int k = 0; k < E; ++k)
-            sg[k] = (own[k] && c[k] != dc) ? live_load<FAST>(&a.Sig[c[k]]) : (ST)0;
-        SC best = score_min<SC>();
-        int bc = INT_MAX;
-        ST hd = 0;
+        // each distinct community is held by the lane that created its slot
+        ST x[E];
+        ST hd = 0, xm = 0;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-            if (!own[k]) continue;
-            if (c[k] == dc) {
-                hd = x[k];
-            } else {
-                const SC sc = (SC)Wv * (SC)x[k] - (SC)kv * (SC)sg[k];
-                if (better(sc, c[k], best, bc)) {
-                    best = sc;
-                    bc = c[k];
-                }
-            }
+            x[k] = own[k] ? (ST)vals[slot[k]] : (ST)0;
+            if (own[k] && c[k] == dc) hd = x[k];
+            if (own[k] && c[k] != dc && x[k] > xm) xm = x[k];
         }
         wave_sync();
 #pragma unroll
@@ -419,19 +450,55 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
                 keys[slot[k]] = -1;
                 vals[slot[k]] = 0;
             }
+        // the group's weight to its own community (one lane holds it) and its
+        // heaviest candidate weight
         for (int o = G / 2; o > 0; o >>= 1) {
-            const SC ob = shfl_xor_t<SC>(best, o);
-            const int oc = __shfl_xor(bc, o, 64);
-            if (better(ob, oc, best, bc)) {
-                best = ob;
-                bc = oc;
-            }
             const ST oh = shfl_xor_t<ST>(hd, o);
-            hd = oh > hd ? oh : hd;  // lanes that saw the own community hold the same total
+            hd = oh > hd ? oh : hd;
+            const ST ox = shfl_xor_t<ST>(xm, o);
+            xm = ox > xm ? ox : xm;
             nonself += __shfl_xor(nonself, o, 64);
         }
+        // totals of the candidates whose score bound reaches the floor: those of
+        // weight at least half the heaviest first, then the rest against the
+        // best score found
+        SC floor = score_floor<C>(Wv, hd, kv, sd);
+        SC best = score_min<SC>();
+        int bc = INT_MAX;
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+            bool rd[E];
+            ST sg[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const bool heavy = x[k] >= xm - x[k];
+                rd[k] = own[k] && c[k] != dc && (ph == 0 ? heavy : !heavy) &&
+                        worth_reading<C>(Wv, x[k], floor);
+            }
+#pragma unroll
+            for (int k = 0; k < E; ++k) sg[k] = rd[k] ? live_load<FAST>(&a.Sig[c[k]]) : (ST)0;
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                if (!rd[k]) continue;
+                ++nk;
+                const SC sc = (SC)Wv * (SC)x[k] - (SC)kv * (SC)sg[k];
+                if (better(sc, c[k], best, bc)) {
+                    best = sc;
+                    bc = c[k];
+                }
+            }
+            for (int o = G / 2; o > 0; o >>= 1) {
+                const SC ob = shfl_xor_t<SC>(best, o);
+                const int oc = __shfl_xor(bc, o, 64);
+                if (better(ob, oc, best, bc)) {
+                    best = ob;
+                    bc = oc;
+                }
+            }
+            if (best > floor) floor = best;
+        }
         SC gain = 0;
-        const bool mv = has && decide<C, FAST>(a, Wv, dc, kv, best, bc, hd, nonself, &gain);
+        const bool mv = has && decide<C, FAST>(a, Wv, dc, kv, best, bc, hd, nonself, sd, &gain);
         if (mv && gl == 0) graph_gain<C>(a, v, gain);
         if (has && gl == 0) {
             ++nv;
@@ -519,6 +586,8 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
     constexpr int NW = BT / 64;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ BlockRed<SC, ST, NW> r;
+    __shared__ ST s_mx[NW];
+    __shared__ SC s_mb[NW];
     typedef typename C::VT VT;
     const int S_max = 1 << log2s_max;
     VT *s_vals = (VT *)smem;
@@ -541,6 +610,7 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
         const ST kv = a.K[v];
         const int64_t Wv = vertex_W(a, v);
         const int log2s = block_log2s(d);
+        const ST sd = live_load<FAST>(&a.Sig[dc]);
         int nonself = 0;
         for (int e0 = threadIdx.x; e0 < d; e0 += 4 * BT) {
             int j[4], c[4];
@@ -557,38 +627,72 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
                 ne += j[k] >= 0 ? 1 : 0;
                 if (c[k] >= 0) {
                     ++nonself;
-                    nk += lds_insert<VT>(s_keys, s_vals, log2s, c[k], (VT)w[k]);
+                    lds_insert<VT>(s_keys, s_vals, log2s, c[k], (VT)w[k]);
                 }
             }
         }
         __syncthreads();
+        const int S = 1 << log2s;
+        // weight to the own community and the heaviest candidate weight
+        ST hd = 0, xm = 0;
+        for (int s = threadIdx.x; s < S; s += BT) {
+            const int k = s_keys[s];
+            if (k < 0) continue;
+            const ST x = (ST)s_vals[s];
+            if (k == dc)
+                hd = x;
+            else if (x > xm)
+                xm = x;
+        }
+        hd = block_max<ST, NW>(hd, s_mx);
+        xm = block_max<ST, NW>(xm, s_mx);
+        // totals of the candidates whose score bound reaches the floor: those of
+        // weight at least half the heaviest first, then the rest against the best
+        // score found (the second scan also clears the table)
+        SC floor = score_floor<C>(Wv, hd, kv, sd);
         SC best = score_min<SC>();
         int bc = INT_MAX;
-        ST hd = 0;
-        for (int s0 = threadIdx.x; s0 < (1 << log2s); s0 += 4 * BT) {
-            int kk[4];
-            ST xx[4], sg[4];
+        for (int ph = 0; ph < 2; ++ph) {
+            for (int s0 = threadIdx.x; s0 < S; s0 += 4 * BT) {
+                int kk[4];
+                ST xx[4], sg[4];
+                bool rd[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int s = s0 + q * BT;
-                kk[q] = s < (1 << log2s) ? s_keys[s] : -1;
-                xx[q] = kk[q] >= 0 ? (ST)s_vals[s] : (ST)0;
-                if (kk[q] >= 0) {
-                    s_keys[s] = -1;
-                    s_vals[s] = 0;
+                for (int q = 0; q < 4; ++q) {
+                    const int s = s0 + q * BT;
+                    kk[q] = s < S ? s_keys[s] : -1;
+                    xx[q] = kk[q] >= 0 ? (ST)s_vals[s] : (ST)0;
+                    if (ph == 1 && kk[q] >= 0) {
+                        s_keys[s] = -1;
+                        s_vals[s] = 0;
+                    }
+                    const bool heavy = xx[q] >= xm - xx[q];
+                    rd[q] = kk[q] >= 0 && kk[q] != dc && (ph == 0 ? heavy : !heavy) &&
+                            worth_reading<C>(Wv, xx[q], floor);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sg[q] = rd[q] ? live_load<FAST>(&a.Sig[kk[q]]) : (ST)0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (!rd[q]) continue;
+                    ++nk;
+                    const SC sc = (SC)Wv * (SC)xx[q] - (SC)kv * (SC)sg[q];
+                    if (better(sc, kk[q], best, bc)) {
+                        best = sc;
+                        bc = kk[q];
+                    }
                 }
             }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                sg[q] = (kk[q] >= 0 && kk[q] != dc) ? live_load<FAST>(&a.Sig[kk[q]]) : (ST)0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) consider<C>(a, Wv, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+            if (ph == 0) {
+                const SC b1 = block_max<SC, NW>(best, s_mb);
+                if (b1 > floor) floor = b1;
+            }
         }
-        block_reduce<SC, ST, NW>(r, best, bc, hd, nonself);
+        block_reduce<SC, ST, NW>(r, best, bc, threadIdx.x == 0 ? hd : (ST)0, nonself);
         if (threadIdx.x == 0) {
             SC gain = 0;
             const bool mv = decide<C, FAST>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0],
-                                                &gain);
+                                            sd, &gain);
             if (mv) graph_gain<C>(a, v, gain);
             r.move = mv ? 1 : 0;
             ++nv;
@@ -675,6 +779,8 @@ __global__ __launch_bounds__(256) void k_hub_fill(MoveArgs<C> a)
     for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
     __syncthreads();
     int32_t *stage = a.hstage + a.hoff[h];
+    const int dc = a.Cp[v];
+    ST hd = 0;  // weight of the slice's entries into the hub's own community
     for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
         const int c = stage[e];
         if (c >= 0) atomicAdd(&hist[part_of(c, parts)], 1);
@@ -704,9 +810,12 @@ __global__ __launch_bounds__(256) void k_hub_fill(MoveArgs<C> a)
                 const int pos = atomicAdd(&hist[part_of(c[k], parts)], 1);
                 a.pk[pos] = c[k];
                 a.pw[pos] = w[k];
+                if (c[k] == dc) hd += w[k];
             }
         }
     }
+    hd = (ST)wave_sum_u64((unsigned long long)(int64_t)hd);
+    if ((threadIdx.x & 63) == 0 && hd != 0) atomic_add_t<ST>(&a.hub_hd[h], hd);
 }
 
 // Hubs, step 3: one workgroup per partition of a queued hub folds the
@@ -737,6 +846,9 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
     const int dc = a.Cp[v];
     const ST kv = a.K[v];
     const int64_t Wv = vertex_W(a, v);
+    // candidates of this partition whose score bound cannot exceed staying are
+    // not read (the hub's weight to its own community is complete after k_hub_fill)
+    const SC floor = score_floor<C>(Wv, a.hub_hd[h], kv, a.Sig[dc]);
     const int pb = a.poff[gp], pn = a.pcount[gp];
     // table of 2^lg slots: twice the pairs (so no overflow) when that fits
     int lg = 8;
@@ -797,6 +909,7 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
         for (int s0 = threadIdx.x; s0 < Su; s0 += 4 * 256) {
             int kk[4];
             ST xx[4], sg[4];
+            bool rd[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int s = s0 + q * 256;
@@ -805,13 +918,15 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
                 if (kk[q] >= 0) {
                     keys[s] = -1;
                     vals[s] = 0;
-                    ++nk;
                 }
+                rd[q] = kk[q] >= 0 && kk[q] != dc && worth_reading<C>(Wv, xx[q], floor);
+                nk += rd[q] ? 1 : 0;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sg[q] = (kk[q] >= 0 && kk[q] != dc) ? a.Sig[kk[q]] : (ST)0;
+            for (int q = 0; q < 4; ++q) sg[q] = rd[q] ? a.Sig[kk[q]] : (ST)0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) consider<C>(a, Wv, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+            for (int q = 0; q < 4; ++q)
+                if (rd[q] || kk[q] == dc) consider<C>(a, Wv, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
         }
     }
     block_reduce<SC, ST, 4>(r, best, bc, hd, nk);
@@ -866,7 +981,8 @@ __global__ __launch_bounds__(HUB_THREADS) void k_move_hub(MoveArgs<C> a)
             // a hub row holds more than the LDS row limit of distinct targets, so
             // it always has an entry other than a self-loop
             SC gain = 0;
-            const bool mv = decide<C, FAST>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], 1, &gain);
+            const bool mv = decide<C, FAST>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], 1,
+                                            FAST ? (ST)0 : a.Sig[dc], &gain);
             if (mv) graph_gain<C>(a, v, gain);
             ++nv;
             if (mv) {
@@ -959,6 +1075,8 @@ void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int3
     // the launch covers sorting slices [slice_base, + sort_slices) and partitions
     // [part_base, + parts): all hubs, or the hubs of one colour class
     const int pb = a.part_base;
+    // (the region holds 8 bytes per vertex, so the size rounds up to whole words)
+    launch_fill_bytes_zero(a.hub_hd, ((int64_t)a.nhubs * (int64_t)sizeof(ST) + 7) & ~(int64_t)7, s);
     if (pb == 0 && a.pcur == a.pcount + parts) {
         launch_fill_bytes_zero(a.pcount + pb, 2 * (int64_t)parts * sizeof(int32_t), s);  // pcount, pcur
     } else {

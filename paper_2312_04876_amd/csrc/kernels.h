@@ -200,6 +200,7 @@ struct MoveArgs {
     typename C::ST *pw;
     void *hpart;                       // HubPart<C> per partition
     uint8_t *hub_act;                  // hub queued in this round (2 once it has moved)
+    typename C::ST *hub_hd;            // per hub: weight of its row into its own community
     int32_t nhubs;
     unsigned long long *spread;        // NSPREAD counter rows of SPREAD_W words
     int32_t bin;                       // degree bin of this launch (counter columns)

@@ -34,7 +34,7 @@ struct Layout {
     size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hstage, hstage_w, wcnt, pk, pw, hsz, hoff, scratch;
-    size_t bincnt, binoff, slA, slB, mpre, hub_act, hpart, pcnt, poff;
+    size_t bincnt, binoff, slA, slB, mpre, hub_act, hub_hd, hpart, pcnt, poff;
     size_t colour, front, corder, kcnt, koff, cbm;  // colour-ordered mode
     int64_t kmax;                              // (colour, bin) keys that fit kcnt / koff
     size_t gid[3], gvb[3], gW, gsum, gst, giter, gcomm, gsig, gs2;  // batches
@@ -102,6 +102,7 @@ Layout make_layout(int32_t n, int64_t nnz, int sb, int32_t G = 0)
     L.slB = take(4 * (n1 + 1));
     L.mpre = take(4 * (n1 + 1));
     L.hub_act = take(n1);
+    L.hub_hd = take(8 * n1);
     L.colour = take(4 * n1);
     L.front = take(4 * 2 * n1);
     L.corder = take(4 * n1);
@@ -268,6 +269,7 @@ struct louvain_ctx {
     void *hpart;
     int32_t *pcnt, *poff;
     uint8_t *hub_act;
+    unsigned char *hub_hd;  // per hub: weight into its own community (moving, 4 or 8 bytes)
     // colour-ordered mode: colour of each row, frontier lists of the colouring,
     // rows sorted by (colour, bin), key counts and offsets (device and host)
     int32_t *colour, *front, *corder, *kcnt, *koff;
@@ -701,6 +703,7 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
     a.htslices = &ctx->sc->hub_tslices;
     a.hpart = ctx->hpart;
     a.hub_act = ctx->hub_act;
+    a.hub_hd = (ST *)ctx->hub_hd;
     a.nhubs = bins_of(ctx, NBINS - 1);
     a.done = &ctx->sc->done;
     a.W = ctx->W;
@@ -1433,6 +1436,7 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->poff = (int32_t *)(b + L.poff);
     ctx->mpre = (int32_t *)(b + L.mpre);
     ctx->hub_act = b + L.hub_act;
+    ctx->hub_hd = b + L.hub_hd;
     ctx->colour = (int32_t *)(b + L.colour);
     ctx->front = (int32_t *)(b + L.front);
     ctx->corder = (int32_t *)(b + L.corder);
@@ -1719,10 +1723,11 @@ int louvain_kernel_stats(louvain_ctx *ctx, louvain_kernel_stat *out, int32_t max
         double bytes = 0.0;
         if (f >= F_MOVE0 && f < F_MOVE0 + NBINS) {
             const unsigned long long *w = ctx->hsc->work[WORK_MOVE + f - F_MOVE0];
-            // per vertex: row offsets 8, K' sb, C' 4, active flag 1; per entry: target 4,
-            // weight, C'[j] 4; per distinct community: Sigma' sb; per move: C' 4, two
-            // Sigma' updates 2*sb, two size updates 8
-            bytes = (double)w[0] * (8 + sb + 4 + 1) + (double)w[1] * (4 + wb_in + 4) +
+            // per vertex: row offsets 8, K' sb, C' 4, its community's Sigma' sb, active flag
+            // 1; per entry: target 4, weight, C'[j] 4; per candidate total read (those whose
+            // score bound reaches the floor): Sigma' sb; per move: C' 4, two Sigma' updates
+            // 2*sb, two size updates 8
+            bytes = (double)w[0] * (8 + 2 * sb + 4 + 1) + (double)w[1] * (4 + wb_in + 4) +
                     (double)w[2] * sb + (double)w[3] * (4 + 2 * sb + 8);
         } else if (f >= F_AGG0 && f < F_AGG0 + NBINS) {
             const unsigned long long *w = ctx->hsc->work[WORK_AGG + f - F_AGG0];
