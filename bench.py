@@ -71,6 +71,9 @@ def parse():
                          "(n log-uniform 200..50,000, mean degree 8..40, p_out/p_in = 0.02) as one "
                          "union run, against the same graphs run one by one")
     ap.add_argument("--batch-nmax", type=int, default=50_000)
+    ap.add_argument("--batch-q-out", default=None, metavar="PATH",
+                    help="write each graph's modularity (union run and one by one) to this JSON "
+                         "file, for comparison with the oracle offline")
     ap.add_argument("--serve", type=float, nargs="*", metavar="RATE",
                     help="only run the serving workload: Poisson arrivals at each RATE jobs/s "
                          "drawn from a pool of SBM and R-MAT graphs")
@@ -383,6 +386,12 @@ def batch_main(args):
     print("one by one: %.1f ms, %.3g edges/s" % (sec_s * 1e3, u.nnz / sec_s), file=sys.stderr,
           flush=True)
     dq = [abs(a - b) for a, b in zip(q_b, q_s)]
+    if args.batch_q_out:
+        with open(args.batch_q_out, "w") as fh:
+            json.dump({"graphs": args.batch, "batch_nmax": args.batch_nmax, "seed": 4,
+                       "mode": args.mode, "round_bits": args.round_bits, "options": uopts,
+                       "q_union": list(map(float, q_b)), "q_one_by_one": list(map(float, q_s))},
+                      fh)
     line = {
         "metric": "edges/s of a batch of graphs (one union run) vs the same graphs run one by one",
         "value": u.nnz / sec_b, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,

@@ -9,7 +9,11 @@ bit-identical under every setting):
 * ``hub_part_pairs``: pairs per hash partition of a hub row in local moving;
 * ``small_level``: a level (in a batch, a graph's part of it) of at most this
   many vertices is moved by one wavefront in one launch instead of by the
-  degree bins' rounds (in fast mode this also means in vertex order).
+  degree bins' rounds.  In deterministic mode this moves work between kernels
+  like the other two knobs; in fast mode it also decides the order of the
+  moves (vertex order instead of thousands of concurrent decisions), which is
+  what keeps the coarse levels of small graphs from herding, so fast mode keeps
+  its built-in value and is tuned over the first two knobs only.
 
 :func:`tune` times every candidate setting on the caller's own graph (or batch
 union) with inputs resident on the GPU and returns the fastest, so a workload
@@ -56,7 +60,8 @@ def candidates(wide: bool) -> List[Tuple[int, int]]:
 def tune(offsets, targets, weights, graph_offsets=None, runs: int = 2, warmup: int = 1,
          cache_path: Optional[str] = None, stream=None, **params) -> Dict:
     """Time every candidate (hub_rows, hub_part_pairs) over `runs` whole runs after
-    `warmup` untimed ones, then every small_level with the best of them; returns
+    `warmup` untimed ones, then (deterministic mode) every small_level with the best
+    of them; returns
     {"hub_rows", "hub_part_pairs", "small_level", "ms", "table", "seconds",
     "signature", "cached"}.  `params` are the run's other parameters."""
     import torch
@@ -98,12 +103,15 @@ def tune(offsets, targets, weights, graph_offsets=None, runs: int = 2, warmup: i
     for rows, pairs in candidates(wide):
         timed(rows, pairs, 0)
     best = min(table, key=lambda r: r["ms"])
-    # the built-in small_level (0) is 1024 in fast mode and none (-1) in deterministic mode
-    builtin = 1024 if params.get("mode") == "fast" else -1
-    for small in SMALL_LEVELS:
-        if small != builtin:
-            timed(best["hub_rows"], best["hub_part_pairs"], small)
-    best = min(table, key=lambda r: r["ms"])
+    # the built-in small_level (0) is 1024 in fast mode and none (-1) in deterministic
+    # mode; only deterministic mode, where it cannot change a result, is tuned over it
+    fast = params.get("mode") == "fast"
+    builtin = 1024 if fast else -1
+    if not fast:
+        for small in SMALL_LEVELS:
+            if small != builtin:
+                timed(best["hub_rows"], best["hub_part_pairs"], small)
+        best = min(table, key=lambda r: r["ms"])
     out = {"hub_rows": best["hub_rows"], "hub_part_pairs": best["hub_part_pairs"],
            "small_level": best["small_level"] or builtin, "ms": best["ms"], "table": table,
            "seconds": time.perf_counter() - t_start, "signature": key, "cached": False}

@@ -74,6 +74,30 @@ __device__ inline int owner_of(const int32_t *incl, int n, int t)
     return lo;
 }
 
+// Entries folded per lane at a time: their targets, weights and target
+// communities are loaded together, so several dependent gathers are in flight
+// per lane instead of one (more in the hub windows, whose large LDS tables
+// leave few workgroups per CU).
+constexpr int AGG_U = 4;
+constexpr int AGG_HUB_U = 16;
+
+// For CSR entries e[] (-1 for none): add(C'[target], weight) for each.
+template <class C, typename VT, int U, class F>
+__device__ inline void fold_entries(const AggArgs<C> &a, const int (&e)[U], F add)
+{
+    int j[U], c[U];
+    VT w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = e[u] >= 0 ? a.tgt[e[u]] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) w[u] = e[u] >= 0 ? (VT)a.w[e[u]] : (VT)0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = j[u] >= 0 ? a.Cp[j[u]] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (c[u] >= 0) add(c[u], w[u]);
+}
+
 // Inclusive prefix sum of x over the G lanes of a group (G <= 64).
 template <int G>
 __device__ inline int group_inclusive_scan(int x, int gl)
@@ -132,10 +156,16 @@ __global__ __launch_bounds__(256) void k_agg_wave(AggArgs<C> a)
             incl[gl] = inc;
             rbs[gl] = rb;
             wave_sync();
-            for (int t = gl; t < total; t += G) {
-                const int L = owner_of(incl, G, t);
-                const int e = rbs[L] + (t - (L ? incl[L - 1] : 0));
-                lds_add<ST>(keys, vals, LOG2S, a.Cp[a.tgt[e]], (ST)a.w[e]);
+            for (int t0 = gl; t0 < total; t0 += AGG_U * G) {
+                int e[AGG_U];
+#pragma unroll
+                for (int u = 0; u < AGG_U; ++u) {
+                    const int t = t0 + u * G;
+                    const int L = t < total ? owner_of(incl, G, t) : 0;
+                    e[u] = t < total ? rbs[L] + (t - (L ? incl[L - 1] : 0)) : -1;
+                }
+                fold_entries<C, ST, AGG_U>(a, e,
+                                           [&](int32_t c, ST w) { lds_add<ST>(keys, vals, LOG2S, c, w); });
             }
             ne_ += total > gl ? (total - gl + G - 1) / G : 0;
             nm_ += mi < me ? 1 : 0;
@@ -233,11 +263,17 @@ __global__ __launch_bounds__(256) void k_agg_block(AggArgs<C> a, int log2s_max)
             s_incl[threadIdx.x] = inc;
             s_rb[threadIdx.x] = rb;
             __syncthreads();
-            for (int t = threadIdx.x; t < total; t += 256) {
-                const int L = owner_of(s_incl, 256, t);
-                const int e = s_rb[L] + (t - (L ? s_incl[L - 1] : 0));
-                lds_add<ST>(s_keys, s_vals, log2s, a.Cp[a.tgt[e]], (ST)a.w[e]);
-                ++ne_;
+            for (int t0 = threadIdx.x; t0 < total; t0 += AGG_U * 256) {
+                int e[AGG_U];
+#pragma unroll
+                for (int u = 0; u < AGG_U; ++u) {
+                    const int t = t0 + u * 256;
+                    const int L = t < total ? owner_of(s_incl, 256, t) : 0;
+                    e[u] = t < total ? s_rb[L] + (t - (L ? s_incl[L - 1] : 0)) : -1;
+                    ne_ += t < total ? 1 : 0;
+                }
+                fold_entries<C, ST, AGG_U>(
+                    a, e, [&](int32_t c, ST w) { lds_add<ST>(s_keys, s_vals, log2s, c, w); });
             }
             __syncthreads();
         }
@@ -279,32 +315,20 @@ __global__ __launch_bounds__(256) void k_agg_block(AggArgs<C> a, int log2s_max)
 // it in LDS and appends its keys to the community's row.
 
 // Walks the flattened entries t in [w0, w1) of community c's member rows
-// (members mb..me, flattened offsets mpre - base): f(t, e) for CSR entry e.
-// All threads of the workgroup call this.
+// (members m0..me, m0 the first whose row reaches past w0; flattened offsets
+// mpre - base): f(e) for AGG_HUB_U CSR entries
+// e[] per thread at a time (-1 past the end).  All threads of the workgroup
+// call this.
 struct Window {
     int32_t start[257];
     int32_t rb[256];
-    int32_t m0;
 };
 
 template <class C, class F>
-__device__ inline void walk_window(const AggArgs<C> &a, Window &W, int mb, int me, int base, int w0,
+__device__ inline void walk_window(const AggArgs<C> &a, Window &W, int m0, int me, int base, int w0,
                                    int w1, unsigned long long *nm_, F f)
 {
-    if (threadIdx.x == 0) {
-        // first member whose row ends after w0
-        int lo = mb, hi = me - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (a.mpre[mid + 1] - base > w0)
-                hi = mid;
-            else
-                lo = mid + 1;
-        }
-        W.m0 = lo;
-    }
-    __syncthreads();
-    int m = W.m0;
+    int m = m0;
     for (;;) {
         const int cnt = min(256, me - m);
         if ((int)threadIdx.x < cnt) {
@@ -318,9 +342,15 @@ __device__ inline void walk_window(const AggArgs<C> &a, Window &W, int mb, int m
         __syncthreads();
         const int t_lo = max(w0, W.start[0]);
         const int t_hi = min(w1, W.start[cnt]);
-        for (int t = t_lo + (int)threadIdx.x; t < t_hi; t += 256) {
-            const int L = owner_slice(W.start, cnt, t);
-            f(t, W.rb[L] + (t - W.start[L]));
+        for (int t0 = t_lo + (int)threadIdx.x; t0 < t_hi; t0 += AGG_HUB_U * 256) {
+            int e[AGG_HUB_U];
+#pragma unroll
+            for (int u = 0; u < AGG_HUB_U; ++u) {
+                const int t = t0 + u * 256;
+                const int L = t < t_hi ? owner_slice(W.start, cnt, t) : 0;
+                e[u] = t < t_hi ? W.rb[L] + (t - W.start[L]) : -1;
+            }
+            f(e);
         }
         const bool more = W.start[cnt] < w1 && m + cnt < me;
         __syncthreads();
@@ -335,7 +365,7 @@ template <class C>
 __device__ inline void agg_window(const AggArgs<C> &a, int nh, int k, int *idx, int *c, int *mb,
                                   int *me, int *base, int *w0, int *w1, int *parts, int *gp0)
 {
-    *idx = owner_slice(a.cslice, nh, k);
+    *idx = a.sown[k];
     *c = a.cbinorder[a.begin + *idx];
     *mb = a.coff[*c];
     *me = a.coff[*c + 1];
@@ -376,9 +406,11 @@ __global__ __launch_bounds__(256) void k_agg_hub_count(AggArgs<C> a, int32_t nh)
     }
     if (threadIdx.x == 0) s_n = 0;
     unsigned long long ne_ = 0, nm_ = 0;
-    walk_window(a, W, mb, me, base, w0, w1, &nm_, [&](int t, int e) {
-        lds_add_n<VT>(keys, vals, (uint32_t)S, a.Cp[a.tgt[e]], (VT)a.w[e]);
-        ++ne_;
+    walk_window(a, W, a.wm0[blockIdx.x], me, base, w0, w1, &nm_, [&](const int (&e)[AGG_HUB_U]) {
+        fold_entries<C, VT, AGG_HUB_U>(a, e, [&](int32_t c, VT w) {
+            lds_add_n<VT>(keys, vals, (uint32_t)S, c, w);
+            ++ne_;
+        });
     });
     int32_t *sk = a.hstage + base + w0;
     ST *sw = a.hstage_w + base + w0;
@@ -444,7 +476,7 @@ __global__ __launch_bounds__(256) void k_agg_hub_part(AggArgs<C> a, int32_t nh)
     __shared__ uint64_t st_lo[40], st_hi[40];
     __shared__ int s_sp, s_cnt, s_over, s_pos, s_base;
     const int gp = (int)blockIdx.x;
-    const int idx = owner_slice(a.tslice, nh, gp);
+    const int idx = a.pown[gp];
     const int c = a.cbinorder[a.begin + idx];
     const int pb = a.poff[gp], pn = a.pcount[gp];
     // table of 2^lg slots: twice the pairs (so no overflow) when that fits
@@ -475,13 +507,24 @@ __global__ __launch_bounds__(256) void k_agg_hub_part(AggArgs<C> a, int32_t nh)
         }
         __syncthreads();
         const bool all = lo == 0 && hi == (1ull << 32);
-        for (int i = threadIdx.x; i < pn; i += 256) {
-            const int32_t key = a.pk[pb + i];
-            if (!all) {
-                const uint64_t x = hash32(mix32((uint32_t)key) ^ 0x5bd1e995u);
-                if (x < lo || x >= hi) continue;
+        for (int i0 = threadIdx.x; i0 < pn; i0 += 4 * 256) {
+            // four pairs per thread loaded together, then inserted
+            int32_t kq[4];
+            ST wq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) kq[q] = i0 + q * 256 < pn ? a.pk[pb + i0 + q * 256] : -1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wq[q] = kq[q] >= 0 ? a.pw[pb + i0 + q * 256] : (ST)0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t key = kq[q];
+                if (key < 0) continue;
+                if (!all) {
+                    const uint64_t x = hash32(mix32((uint32_t)key) ^ 0x5bd1e995u);
+                    if (x < lo || x >= hi) continue;
+                }
+                if (!lds_insert_capped<ST>(keys, vals, lg, key, wq[q], &s_cnt, capu)) s_over = 1;
             }
-            if (!lds_insert_capped<ST>(keys, vals, lg, key, a.pw[pb + i], &s_cnt, capu)) s_over = 1;
         }
         __syncthreads();
         if (s_over) {
@@ -516,6 +559,26 @@ __global__ __launch_bounds__(256) void k_agg_hub_part(AggArgs<C> a, int32_t nh)
     emitted = wave_sum_u64(emitted);
     if ((threadIdx.x & 63) == 0 && emitted) atomicAdd(&a.work[3], emitted);
     if (threadIdx.x == 0 && gp == a.tslice[idx]) atomicAdd(&a.work[0], 1ull);
+}
+
+// First member of each window (one thread per window): the first member of its
+// community whose row ends after the window's first flattened entry.
+template <class C>
+__global__ __launch_bounds__(256) void k_window_first_member(AggArgs<C> a, int32_t nh, int32_t windows)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < windows; k += gridDim.x * blockDim.x) {
+        int idx, c, mb, me, base, w0, w1, parts, gp0;
+        agg_window(a, nh, k, &idx, &c, &mb, &me, &base, &w0, &w1, &parts, &gp0);
+        int lo = mb, hi = me - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (a.mpre[mid + 1] - base > w0)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        a.wm0[k] = lo;
+    }
 }
 
 inline int agg_grid(int count, int per_block)
@@ -584,6 +647,9 @@ void launch_aggregate_hub(const AggArgs<C> &a, int32_t sort_slices, int32_t part
     if (a.count <= 0 || sort_slices <= 0 || parts <= 0) return;
     typedef typename C::ST ST;
     launch_fill_bytes_zero(a.pcount, 2 * (int64_t)parts * sizeof(int32_t), s);  // pcount, pcur
+    launch_owner_map(a.cslice, a.count, sort_slices, a.sown, s);
+    launch_owner_map(a.tslice, a.count, parts, a.pown, s);
+    k_window_first_member<C><<<(sort_slices + 255) / 256, 256, 0, s>>>(a, a.count, sort_slices);
     if (sizeof(ST) > 4 && wmax > 0 && wmax * AGG_PSLICE < ((int64_t)1 << 31))
         launch_agg_hub_count<C, int32_t>(a, sort_slices, s);
     else

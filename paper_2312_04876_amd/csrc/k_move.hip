@@ -715,7 +715,7 @@ template <class C>
 __device__ inline bool hub_slice(const MoveArgs<C> &a, int k, int *h, int *v, int *beg, int *e0,
                                  int *e1, int *parts, int *gp0)
 {
-    *h = owner_slice(a.hslice, a.nhubs, k);
+    *h = a.sown[k];
     if (!a.hub_act[*h]) return false;
     *v = a.binorder[a.list_begin + *h];
     *beg = a.off[*v];
@@ -840,7 +840,7 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
     __shared__ int s_sp, s_cnt, s_over;
     if (*a.done) return;
     const int gp = (int)blockIdx.x + a.part_base;
-    const int h = owner_slice(a.htslice, a.nhubs, gp);
+    const int h = a.pown[gp];
     if (!a.hub_act[h]) return;
     const int v = a.binorder[a.list_begin + h];
     const int dc = a.Cp[v];
@@ -880,13 +880,24 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
         }
         __syncthreads();
         const bool all = lo == 0 && hi == (1ull << 32);
-        for (int i = threadIdx.x; i < pn; i += 256) {
-            const int32_t c = a.pk[pb + i];
-            if (!all) {
-                const uint64_t x = hash32(mix32((uint32_t)c) ^ 0x5bd1e995u);
-                if (x < lo || x >= hi) continue;
+        for (int i0 = threadIdx.x; i0 < pn; i0 += 4 * 256) {
+            // four pairs per thread loaded together, then inserted
+            int32_t kq[4];
+            ST wq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) kq[q] = i0 + q * 256 < pn ? a.pk[pb + i0 + q * 256] : -1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wq[q] = kq[q] >= 0 ? a.pw[pb + i0 + q * 256] : (ST)0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t c = kq[q];
+                if (c < 0) continue;
+                if (!all) {
+                    const uint64_t x = hash32(mix32((uint32_t)c) ^ 0x5bd1e995u);
+                    if (x < lo || x >= hi) continue;
+                }
+                if (!lds_insert_capped<VT>(keys, vals, lg, c, (VT)wq[q], &s_cnt, capu)) s_over = 1;
             }
-            if (!lds_insert_capped<VT>(keys, vals, lg, c, (VT)a.pw[pb + i], &s_cnt, capu)) s_over = 1;
         }
         __syncthreads();
         if (s_over) {

@@ -283,6 +283,16 @@ __global__ __launch_bounds__(256) void k_bin_fill(int32_t n, const int32_t *off,
 }
 
 
+// owner[k] = h with start[h] <= k < start[h + 1], for k < total: one thread per
+// k (a giant hub owns hundreds of thousands of slices, so threads per range would
+// leave one thread writing them all).
+__global__ void k_owner_map(const int32_t *start, int32_t n, int32_t total, int32_t *owner)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x)
+        owner[k] = owner_slice(start, n, (int)k);
+}
+
 __global__ void k_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he,
                                  const int32_t *off, const int32_t *deg, int stbytes,
                                  int64_t *ent, int32_t *slices, int32_t *parts, int slice,
@@ -995,6 +1005,11 @@ void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s)
     // bytes is a multiple of 8 for every caller (regions are 256-byte aligned)
     const int64_t n = bytes / 8;
     if (n > 0) k_zero_u64<<<grid_for(n, 256), 256, 0, s>>>((unsigned long long *)p, n);
+}
+
+void launch_owner_map(const int32_t *start, int32_t n, int32_t total, int32_t *owner, hipStream_t s)
+{
+    if (n > 0 && total > 0) k_owner_map<<<grid_for(total, 256), 256, 0, s>>>(start, n, total, owner);
 }
 
 void launch_iota(int32_t *p, int64_t n, hipStream_t s)

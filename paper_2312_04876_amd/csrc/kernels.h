@@ -60,6 +60,11 @@ void launch_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he, cons
                            int32_t *parts, hipStream_t s, int slice = HUB_PSLICE,
                            int per_part = 0);
 
+// owner[k] = h for every k in [start[h], start[h + 1]) (the last range ends at
+// total): the hub, or hub community, of each sorting slice or partition, so the
+// sorting kernels read it instead of searching start[].
+void launch_owner_map(const int32_t *start, int32_t n, int32_t total, int32_t *owner, hipStream_t s);
+
 // mdeg[m] = row length of members[m].
 void launch_member_degrees(int32_t n, const int32_t *members, const int32_t *off,
                            const int32_t *deg, int32_t *mdeg, hipStream_t s);
@@ -193,6 +198,7 @@ struct MoveArgs {
     const int64_t *hoff;               // first staged entry per hub (scan of row lengths)
     const int32_t *hslice;             // first sorting slice per hub (HUB_PSLICE entries)
     const int32_t *htslice;            // first partition per hub
+    const int32_t *sown, *pown;        // hub of each sorting slice / of each partition
     const unsigned long long *htslices;  // total partitions
     int32_t slice_base, part_base;     // first sorting slice and partition of this launch's hubs
     int32_t *pcount, *pcur, *poff;     // pairs per partition, fill cursors, offsets
@@ -331,6 +337,8 @@ struct AggArgs {
     // hub bin: flattened member rows counting-sorted into partitions by community
     const int32_t *mpre;              // exclusive scan of member row lengths
     const int32_t *cslice, *tslice;   // first sorting slice / partition per community
+    int32_t *sown, *pown;             // community (in the bin) of each window / partition
+    int32_t *wm0;                     // first member whose row reaches into each window
     const unsigned long long *tslices;  // total partitions
     int32_t *hstage;                  // distinct pairs of each window (at its flattened offset)
     typename C::ST *hstage_w;

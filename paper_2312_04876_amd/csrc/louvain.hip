@@ -34,7 +34,7 @@ struct Layout {
     size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hstage, hstage_w, wcnt, pk, pw, hsz, hoff, scratch;
-    size_t bincnt, binoff, slA, slB, mpre, hub_act, hub_hd, hpart, pcnt, poff;
+    size_t bincnt, binoff, slA, slB, mpre, hub_act, hub_hd, hpart, pcnt, poff, sown, pown, wm0;
     size_t colour, front, corder, kcnt, koff, cbm;  // colour-ordered mode
     int64_t kmax;                              // (colour, bin) keys that fit kcnt / koff
     size_t gid[3], gvb[3], gW, gsum, gst, giter, gcomm, gsig, gs2;  // batches
@@ -130,6 +130,13 @@ Layout make_layout(int32_t n, int64_t nnz, int sb, int32_t G = 0)
     L.hpart = take(32 * parts);
     L.pcnt = take(4 * 2 * parts);  // pcount then pcur
     L.poff = take(4 * parts);
+    // owner of each partition, and of each sorting slice or window with the first
+    // member reaching into it (hubs and hub communities hold more than 2048 entries,
+    // so there are fewer than nnz/8192 + nnz/2048 slices and nnz/4096 + nnz/2048
+    // windows)
+    L.pown = take(4 * parts);
+    L.sown = take(4 * (z / 1024 + 64));
+    L.wm0 = take(4 * (z / 1024 + 64));
     L.total = cur;
     return L;
 }
@@ -268,6 +275,8 @@ struct louvain_ctx {
     int32_t *bincnt, *binoff, *slA, *slB, *mpre;
     void *hpart;
     int32_t *pcnt, *poff;
+    int32_t *sown, *pown, *wm0;  // owners of hub slices / partitions, first member per window
+    int64_t owner_cap, part_cap; // their capacities
     uint8_t *hub_act;
     unsigned char *hub_hd;  // per hub: weight into its own community (moving, 4 or 8 bytes)
     // colour-ordered mode: colour of each row, frontier lists of the colouring,
@@ -518,6 +527,12 @@ int setup_level(louvain_ctx *ctx)
         if (hubs > 0) {
             ctx->hub_slices = (int32_t)ctx->hsc->hub_slices;
             ctx->hub_tslices = (int32_t)ctx->hsc->hub_tslices;
+            // excluded by the layout's bounds on slices and partitions
+            if (ctx->hub_slices > ctx->owner_cap || ctx->hub_tslices > ctx->part_cap)
+                return LOUVAIN_EINVAL;
+            launch_owner_map(ctx->slA, hubs, ctx->hub_slices, ctx->sown, s);
+            launch_owner_map(ctx->slB, hubs, ctx->hub_tslices, ctx->pown, s);
+            CKL();
         }
         if (want_kmax) ctx->kmax_in = ctx->hsc->kmax;
     }
@@ -631,6 +646,10 @@ int colour_level(louvain_ctx *ctx)
         for (int h = 0; h < hubs; ++h) sorted[h] = ids[idx[h]];
         CK(hipMemcpyAsync(hub_ids, sorted.data(), hubs * sizeof(int32_t), hipMemcpyHostToDevice, s));
         TRY(hub_layout<C>(ctx));
+        // same totals as before the reordering; the owners follow the new order
+        launch_owner_map(ctx->slA, hubs, ctx->hub_slices, ctx->sown, s);
+        launch_owner_map(ctx->slB, hubs, ctx->hub_tslices, ctx->pown, s);
+        CKL();
         ctx->hub_sl_h.assign((size_t)hubs + 1, 0);
         ctx->hub_pt_h.assign((size_t)hubs + 1, 0);
         CK(hipMemcpyAsync(ctx->hub_sl_h.data(), ctx->slA, ((size_t)hubs + 1) * sizeof(int32_t),
@@ -700,6 +719,8 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
     a.hoff = ctx->hoff;
     a.hslice = ctx->slA;
     a.htslice = ctx->slB;
+    a.sown = ctx->sown;
+    a.pown = ctx->pown;
     a.htslices = &ctx->sc->hub_tslices;
     a.hpart = ctx->hpart;
     a.hub_act = ctx->hub_act;
@@ -1059,6 +1080,8 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
         TRY(read_scalars(ctx));
         row_slices = (int32_t)ctx->hsc->hub_slices;
         table_slices = (int32_t)ctx->hsc->hub_tslices;
+        // excluded by the layout's bounds on windows and partitions
+        if (row_slices > ctx->owner_cap || table_slices > ctx->part_cap) return LOUVAIN_EINVAL;
     }
     unsigned long long emitted0 = 0;
     for (int b = 0; b < NBINS; ++b) emitted0 += ctx->hsc->work[WORK_AGG + b][3];
@@ -1087,6 +1110,9 @@ int aggregate_phase(louvain_ctx *ctx, int32_t *communities, int32_t *stop)
     g.mpre = ctx->mpre;
     g.cslice = ctx->slA;
     g.tslice = ctx->slB;
+    g.sown = ctx->sown;
+    g.pown = ctx->pown;
+    g.wm0 = ctx->wm0;
     g.ncomm = nc;
     for (int b = 0; b < NBINS; ++b) {
         g.begin = cb.start[b];
@@ -1434,6 +1460,11 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->hpart = (void *)(b + L.hpart);
     ctx->pcnt = (int32_t *)(b + L.pcnt);
     ctx->poff = (int32_t *)(b + L.poff);
+    ctx->sown = (int32_t *)(b + L.sown);
+    ctx->pown = (int32_t *)(b + L.pown);
+    ctx->wm0 = (int32_t *)(b + L.wm0);
+    ctx->owner_cap = (nnz > 0 ? nnz : 1) / 1024 + 64;  // as sized in make_layout
+    ctx->part_cap = (nnz > 0 ? nnz : 1) / 512 + 64;
     ctx->mpre = (int32_t *)(b + L.mpre);
     ctx->hub_act = b + L.hub_act;
     ctx->hub_hd = b + L.hub_hd;

@@ -565,7 +565,12 @@ def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
     res = autotune.tune(off, tgt, w, runs=1, warmup=1, cache_path=cache, mode="fast")
     print("autotune", res["hub_rows"], res["hub_part_pairs"], res["table"], flush=True)
     assert (res["hub_rows"], res["hub_part_pairs"]) in autotune.candidates(wide=False)
-    assert res["small_level"] in (-1, 256, 1024)
-    assert len(res["table"]) == 6 + 2 and not res["cached"]
+    # fast mode keeps its small-level kernel (a quality setting there): six candidates
+    assert res["small_level"] == 1024
+    assert len(res["table"]) == 6 and not res["cached"]
     again = autotune.tune(off, tgt, w, cache_path=cache, mode="fast")
     assert again["cached"] and again["hub_rows"] == res["hub_rows"]
+    # deterministic mode also times the small-level settings (results never change)
+    det = autotune.tune(off, tgt, w, runs=1, warmup=1, mode="deterministic")
+    assert det["small_level"] in (-1, 256, 1024)
+    assert len(det["table"]) == 6 + 2 and not det["cached"]
