@@ -107,7 +107,7 @@ __device__ inline bool decide(const MoveArgs<C> &a, int64_t W, int dc, typename 
 
 // Fast mode applies a move at once: both community weights and both sizes
 // (HBM atomics), then the label, so every vertex decided later reads the new
-// state.  The label goes last, after an agent-scope release fence: a reader that
+// state.  The label goes last, once the atomics have completed: a reader that
 // sees the new label of a neighbour must not score its new community
 // against a total that still lacks the neighbour's weight (with the label
 // ahead of the totals, every such reader over-rates the mover's community
