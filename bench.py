@@ -127,7 +127,7 @@ def _pmc_rows(d):
     return rows
 
 
-def pmc_summary(dirs, out):
+def pmc_summary(dirs, out, workload=None):
     """Per-kernel HBM traffic per dispatch from FETCH_SIZE / WRITE_SIZE runs, scaled by what the
     same counters read for the copy probe (bytes actually moved / counter bytes)."""
     import re
@@ -174,20 +174,22 @@ def pmc_summary(dirs, out):
                                                     for k in ks) / max(launches, 1)
             fam[family]["memory_side_atomics_per_launch"] = sum(
                 kernels[k].get("atomics_memory_side", 0.0) for k in ks) / max(launches, 1)
-    data = {"sources_sha256": sources_digest(), "fetch_factor": ff, "write_factor": wf,
-            "families": fam, "kernels": kernels}
+    data = {"sources_sha256": sources_digest(), "workload": workload, "fetch_factor": ff,
+            "write_factor": wf, "families": fam, "kernels": kernels}
     with open(out, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
     print(json.dumps({"fetch_factor": ff, "write_factor": wf, "families": fam}, indent=1))
 
 
-def measured_traffic(family, path, key="bytes_per_launch"):
+def measured_traffic(family, path, key="bytes_per_launch", workload=None):
     """HBM bytes (or, with key, another per-launch figure) of `family` from the PMC summary,
-    if it was taken on these sources."""
+    if it was taken on these sources (and on this workload)."""
     if not os.path.exists(path):
         return None
     data = json.load(open(path))
     if data.get("sources_sha256") != sources_digest():
+        return None
+    if workload is not None and data.get("workload") not in (None, workload):
         return None
     f = data.get("families", {}).get(family)
     return f.get(key) if f else None
@@ -587,7 +589,7 @@ def main():
         if len(args.pmc_summary) not in (4, 5):
             print("--pmc-summary takes 4 or 5 directories", file=sys.stderr)
             sys.exit(2)
-        pmc_summary(args.pmc_summary, args.pmc_out or os.path.join(
+        pmc_summary(args.pmc_summary, workload=args.workload, out=args.pmc_out or os.path.join(
             ROOT, "profiles", "%s_%s_pmc.json" % (args.workload, args.mode)))
         return
     if args.gpus != 1:
@@ -724,7 +726,9 @@ def measure(args, csr, name, steps, warmup):
     prof_sec = None
     phases = None
     scan_rate = None
-    pmc_path = args.pmc_out or os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (name, args.mode))
+    pmc_path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (name, args.mode))
+    if args.pmc_out and name == args.workload:
+        pmc_path = args.pmc_out
     if not args.no_profile:
         # timed region 2: same steps with HIP events around every kernel launch
         ctxp = P.Louvain(off, tgt, w, profile=True, **opts)
@@ -747,8 +751,8 @@ def measure(args, csr, name, steps, warmup):
             gbs = dom["bytes_per_step"] / (dom["ms_per_step"] * 1e-3) / 1e9 \
                 if dom["ms_per_step"] else 0.0
             per_launch_s = dom["ms_per_step"] * 1e-3 * steps / max(dom["launches"], 1)
-            traffic = measured_traffic(dom["name"], pmc_path)
-            atomics = measured_traffic(dom["name"], pmc_path, "atomics_per_launch")
+            traffic = measured_traffic(dom["name"], pmc_path, workload=name)
+            atomics = measured_traffic(dom["name"], pmc_path, "atomics_per_launch", workload=name)
             return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": dom["name"],
