@@ -19,11 +19,11 @@ def families_of(name):
 
 
 def test_profiled_kernels_map_to_at_most_one_family():
-    data = json.load(open(os.path.join(ROOT, "profiles", "rmat22_fast_pmc.json")))
+    data = json.load(open(os.path.join(ROOT, "profiles", "rmat24_fast_pmc.json")))
     for name in data["kernels"]:
         assert len(families_of(name)) <= 1, name
     fams = data["families"]
-    assert "move_bin2_16lanes" in fams
+    assert "move_bin6_hub" in fams and "agg_bin6_hub" in fams
     for f, rec in fams.items():
         assert rec["launches"] > 0 and rec["bytes_per_launch"] > 0, f
 
@@ -48,6 +48,6 @@ def test_every_configuration_maps_to_its_family():
 
 
 def test_copy_probe_calibration_is_recorded():
-    data = json.load(open(os.path.join(ROOT, "profiles", "rmat22_fast_pmc.json")))
+    data = json.load(open(os.path.join(ROOT, "profiles", "rmat24_fast_pmc.json")))
     # FETCH_SIZE counts half of what a plain copy reads on this part; WRITE_SIZE all it writes
     assert abs(data["fetch_factor"] - 2.0) < 0.05 and abs(data["write_factor"] - 1.0) < 0.05
