@@ -128,8 +128,9 @@ def test_sbm_recovers_planted_quality():
 @pytest.mark.parametrize("mp", [1, 2, 3])
 @pytest.mark.parametrize("mode", ["seq", "sync"])
 def test_pass_limit_lookup_applies_each_pass_once(wl, mp, mode):
-    # Alg. 1 when the pass loop runs out of passes (reading g4): the membership is the
-    # composition of each pass's renumbered labels, applied once per pass.  The
+    # Alg. 1 when the pass loop runs out of passes (the final lookup runs only when the
+    # loop ends early): the membership is the composition of each pass's renumbered
+    # labels, applied once per pass.  The
     # composition is rebuilt here from single steps (one local-moving phase per level,
     # numpy's dense renumbering, the aggregated level) and must equal the C pass loop's
     # result; Q(G, membership) must equal the modularity of the last aggregated level
