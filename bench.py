@@ -52,7 +52,8 @@ def parse():
                     help="pick the hub threshold and hub partition size by timing the candidates "
                          "on this workload first (paper_2312_04876_amd.autotune)")
     ap.add_argument("--round-bits", type=int, default=None,
-                    help="2^round_bits rounds per iteration (default 1)")
+                    help="2^round_bits rounds per iteration (default: the library's, 3 in fast "
+                         "mode on one graph, else 1)")
     ap.add_argument("--cpu-baseline", default="same",
                     help="workload the oracle is timed on: 'same' (the benchmark workload, "
                          "one whole run), a workload name, or 'none'")
@@ -563,7 +564,10 @@ def dynamic_main(args):
 def main():
     args = parse()
     if args.round_bits is None:
-        args.round_bits = 1
+        # the library's default: 8 rounds for one graph in fast mode, else 2 (batches and
+        # serving run batches)
+        single = not args.batch and args.serve is None
+        args.round_bits = 3 if args.mode == "fast" and single else 1
     if args.dynamic:
         if args.gpus != 1:
             print("bench.py measures one GPU; use --gpus 1", file=sys.stderr)

@@ -95,7 +95,8 @@ typedef struct {
     double tolerance_drop;        /* tau /= tolerance_drop after each pass (Alg. 1 threshold scaling) */
     double aggregation_tolerance; /* stop when |communities| / |vertices| of the level > this (Alg. 1) */
     uint64_t seed;                /* key of the round hash and of the colouring priority */
-    int32_t round_bits;           /* 0 .. 4: 2^round_bits rounds per iteration (default 1) */
+    int32_t round_bits;           /* 0 .. 4: 2^round_bits rounds per iteration; -1 (default): the
+                                     mode's own, 3 in LOUVAIN_FAST on one graph, else 1 */
     int32_t profile;              /* 1: time every kernel with HIP events (louvain_kernel_stats) */
     /* Scheduling knobs (results do not depend on them; deterministic modes stay
      * bit-exact): 0 keeps the built-in choice. */

@@ -162,7 +162,7 @@ def _check(code: int, where: str):
 
 def make_params(mode="deterministic", max_passes=10, max_iterations=20, prune=True,
                 tolerance=0.01, tolerance_drop=10.0, aggregation_tolerance=0.8, seed=0,
-                round_bits=1, profile=False, hub_rows=0, hub_part_pairs=0,
+                round_bits=-1, profile=False, hub_rows=0, hub_part_pairs=0,
                 small_level=0) -> CParams:
     p = CParams()
     load_library().louvain_default_params(ctypes.byref(p))

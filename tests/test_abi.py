@@ -41,7 +41,8 @@ def test_default_params_are_the_papers(lib):
     lib.louvain_default_params(ctypes.byref(p))
     assert (p.max_iterations, p.prune, p.tolerance, p.tolerance_drop,
             p.aggregation_tolerance) == (20, 1, 0.01, 10.0, 0.8)
-    assert p.mode == P.DETERMINISTIC and p.max_passes == 10 and p.round_bits == 1
+    # round_bits -1: the mode's own round count (8 rounds for one graph in fast mode, else 2)
+    assert p.mode == P.DETERMINISTIC and p.max_passes == 10 and p.round_bits == -1
 
 
 def test_workspace_size_checks(lib):
@@ -78,9 +79,16 @@ def test_init_rejects_bad_arguments_without_a_gpu(lib):
                             None) == P.binding.EOVERFLOW
     assert lib.louvain_init(ctypes.byref(ctx), 4, 8, fake, fake, fake, fake, 16, None, None) == \
         P.binding.ENOSPC
-    bad = P.make_params(round_bits=9)
-    assert lib.louvain_init(ctypes.byref(ctx), 4, 8, fake, fake, fake, fake, 1 << 40,
-                            ctypes.byref(bad), None) == P.binding.EINVAL
+    out = ctypes.c_size_t()
+    for rb in (9, -2):
+        bad = P.make_params(round_bits=rb)
+        assert lib.louvain_init(ctypes.byref(ctx), 4, 8, fake, fake, fake, fake, 1 << 40,
+                                ctypes.byref(bad), None) == P.binding.EINVAL
+        assert lib.louvain_workspace_size(4, 8, 8, ctypes.byref(bad), ctypes.byref(out)) == \
+            P.binding.EINVAL
+    for rb in (-1, 0, 4):
+        assert lib.louvain_workspace_size(4, 8, 8, ctypes.byref(P.make_params(round_bits=rb)),
+                                          ctypes.byref(out)) == P.binding.OK
     assert ctx.value is None
 
 

@@ -161,13 +161,12 @@ def test_batch_fast_quality():
 
 
 def test_batch_fast_quality_on_the_batch_recipe():
-    # fast mode (the default two rounds per iteration) over a union of 128 SBMs of the
+    # fast mode (its default rounds for batches, two per iteration) over a union of 128 SBMs of the
     # batch recipe: every graph ends no more than 0.01 below the sequential oracle.  Where
     # a graph does end below its oracle run by more, the bar is the lowest Q the
     # sequential oracle itself reaches over eight relabellings of that graph: on this
     # recipe the sequential method alone spreads up to 0.08 over vertex orders (3 of 128
     # graphs more than 0.01)
-    round_bits = 1
     u, go, specs = graphgen.batch_sbm(128, seed=4, n_max=20000)
     graphs = []
     for g in range(128):
@@ -176,7 +175,7 @@ def test_batch_fast_quality_on_the_batch_recipe():
         graphs.append(graphgen.CSR(b - a, (u.offsets[a:b + 1] - e0).astype(np.int64),
                                    (u.targets[e0:e1] - a).astype(np.int32), u.weights[e0:e1].copy(),
                                    "g%d" % g))
-    parts, qs, _ = run_batch(graphs, mode="fast", round_bits=round_bits)
+    parts, qs, _ = run_batch(graphs, mode="fast")
     d = []
     for g, csr in enumerate(graphs):
         og = _og(csr)
@@ -189,8 +188,8 @@ def test_batch_fast_quality_on_the_batch_recipe():
                   (g, qs[g], q_seq, floor), flush=True)
             assert qs[g] >= floor - 0.01, (g, qs[g], q_seq, floor)
     d = np.array(d)
-    print("fast batch (%d rounds) vs sequential oracle: worst %.4f, mean %.4f, below 0.01: %d" %
-          (1 << round_bits, d.min(), d.mean(), int((d < -0.01).sum())), flush=True)
+    print("fast batch vs sequential oracle: worst %.4f, mean %.4f, below 0.01: %d" %
+          (d.min(), d.mean(), int((d < -0.01).sum())), flush=True)
 
 
 def test_batch_rejects_an_edge_between_graphs():
