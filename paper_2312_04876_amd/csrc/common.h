@@ -153,6 +153,8 @@ struct DevScalars {
     unsigned long long scan_total;
     unsigned long long hub_slices;   // row slices of the hub bin (sum over hubs)
     unsigned long long hub_tslices;  // table slices of the hub bin
+    unsigned long long act_slices;   // sorting slices / partitions of the round's queued hubs
+    unsigned long long act_parts;
     unsigned long long W;
     unsigned long long sigma;       // sum of intra-community entries
     unsigned long long s2[2];       // 128-bit sum of Sigma_c^2
@@ -167,7 +169,7 @@ struct DevScalars {
 };
 
 // Work-counter slots (DevScalars::work[k]): move bins 0..NBINS-1
-// [vertices, entries, distinct communities, moves, -], aggregation bins
+// [vertices, entries, community totals read, moves, -], aggregation bins
 // NBINS..2*NBINS-1 [communities, members, entries, emitted, -].
 constexpr int WORK_MOVE = 0;
 constexpr int WORK_AGG = NBINS;

@@ -735,33 +735,37 @@ __global__ __launch_bounds__(256) void k_hub_count(MoveArgs<C> a)
 {
     __shared__ int32_t hist[HUB_MAXP];
     if (*a.done) return;
-    int h, v, beg, e0, e1, parts, gp0;
-    if (!hub_slice(a, (int)blockIdx.x + a.slice_base, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
-    for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
-    __syncthreads();
-    int32_t *stage = a.hstage + a.hoff[h];
+    const int na = (int)*a.n_act_s;
     unsigned long long ne = 0;
-    for (int c0 = e0; c0 < e1; c0 += 256 * 8) {
-        int j[8], c[8];
+    for (int q = blockIdx.x; q < na; q += gridDim.x) {  // uniform over the workgroup
+        int h, v, beg, e0, e1, parts, gp0;
+        if (!hub_slice(a, a.act_s[q], &h, &v, &beg, &e0, &e1, &parts, &gp0)) continue;
+        for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
+        __syncthreads();
+        int32_t *stage = a.hstage + a.hoff[h];
+        for (int c0 = e0; c0 < e1; c0 += 256 * 8) {
+            int j[8], c[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = c0 + (int)threadIdx.x + k * 256;
-            j[k] = e < e1 ? a.tgt[beg + e] : -1;
+            for (int k = 0; k < 8; ++k) {
+                const int e = c0 + (int)threadIdx.x + k * 256;
+                j[k] = e < e1 ? a.tgt[beg + e] : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = c0 + (int)threadIdx.x + k * 256;
+                if (j[k] < 0) continue;
+                ++ne;
+                stage[e] = c[k];
+                if (c[k] >= 0) atomicAdd(&hist[part_of(c[k], parts)], 1);
+            }
         }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) c[k] = (j[k] >= 0 && j[k] != v) ? a.Cp[j[k]] : -1;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = c0 + (int)threadIdx.x + k * 256;
-            if (j[k] < 0) continue;
-            ++ne;
-            stage[e] = c[k];
-            if (c[k] >= 0) atomicAdd(&hist[part_of(c[k], parts)], 1);
-        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < parts; p += 256)
+            if (hist[p]) atomicAdd(&a.pcount[gp0 + p], hist[p]);
+        __syncthreads();  // hist is cleared for the next slice
     }
-    __syncthreads();
-    for (int p = threadIdx.x; p < parts; p += 256)
-        if (hist[p]) atomicAdd(&a.pcount[gp0 + p], hist[p]);
     ne = wave_sum_u64(ne);
     if ((threadIdx.x & 63) == 0 && ne) atomicAdd(&counter_row(a)[2 + 4 * a.bin + 1], ne);
 }
@@ -774,48 +778,52 @@ __global__ __launch_bounds__(256) void k_hub_fill(MoveArgs<C> a)
     typedef typename C::ST ST;
     __shared__ int32_t hist[HUB_MAXP];
     if (*a.done) return;
-    int h, v, beg, e0, e1, parts, gp0;
-    if (!hub_slice(a, (int)blockIdx.x + a.slice_base, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
-    for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
-    __syncthreads();
-    int32_t *stage = a.hstage + a.hoff[h];
-    const int dc = a.Cp[v];
-    ST hd = 0;  // weight of the slice's entries into the hub's own community
-    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
-        const int c = stage[e];
-        if (c >= 0) atomicAdd(&hist[part_of(c, parts)], 1);
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < parts; p += 256)
-        if (hist[p]) hist[p] = a.poff[gp0 + p] + atomicAdd(&a.pcur[gp0 + p], hist[p]);
-    __syncthreads();
-    for (int c0 = e0; c0 < e1; c0 += 256 * 8) {
-        int c[8];
-        ST w[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = c0 + (int)threadIdx.x + k * 256;
-            c[k] = e < e1 ? stage[e] : -1;
+    const int na = (int)*a.n_act_s;
+    for (int q = blockIdx.x; q < na; q += gridDim.x) {  // uniform over the workgroup
+        int h, v, beg, e0, e1, parts, gp0;
+        if (!hub_slice(a, a.act_s[q], &h, &v, &beg, &e0, &e1, &parts, &gp0)) continue;
+        for (int p = threadIdx.x; p < parts; p += 256) hist[p] = 0;
+        __syncthreads();
+        int32_t *stage = a.hstage + a.hoff[h];
+        const int dc = a.Cp[v];
+        ST hd = 0;  // weight of the slice's entries into the hub's own community
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+            const int c = stage[e];
+            if (c >= 0) atomicAdd(&hist[part_of(c, parts)], 1);
         }
+        __syncthreads();
+        for (int p = threadIdx.x; p < parts; p += 256)
+            if (hist[p]) hist[p] = a.poff[gp0 + p] + atomicAdd(&a.pcur[gp0 + p], hist[p]);
+        __syncthreads();
+        for (int c0 = e0; c0 < e1; c0 += 256 * 8) {
+            int c[8];
+            ST w[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = c0 + (int)threadIdx.x + k * 256;
-            w[k] = c[k] >= 0 ? (ST)a.w[beg + e] : (ST)0;
-        }
+            for (int k = 0; k < 8; ++k) {
+                const int e = c0 + (int)threadIdx.x + k * 256;
+                c[k] = e < e1 ? stage[e] : -1;
+            }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = c0 + (int)threadIdx.x + k * 256;
-            if (e >= e1) continue;
-            if (c[k] >= 0) {
-                const int pos = atomicAdd(&hist[part_of(c[k], parts)], 1);
-                a.pk[pos] = c[k];
-                a.pw[pos] = w[k];
-                if (c[k] == dc) hd += w[k];
+            for (int k = 0; k < 8; ++k) {
+                const int e = c0 + (int)threadIdx.x + k * 256;
+                w[k] = c[k] >= 0 ? (ST)a.w[beg + e] : (ST)0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = c0 + (int)threadIdx.x + k * 256;
+                if (e >= e1) continue;
+                if (c[k] >= 0) {
+                    const int pos = atomicAdd(&hist[part_of(c[k], parts)], 1);
+                    a.pk[pos] = c[k];
+                    a.pw[pos] = w[k];
+                    if (c[k] == dc) hd += w[k];
+                }
             }
         }
+        hd = (ST)wave_sum_u64((unsigned long long)(int64_t)hd);
+        if ((threadIdx.x & 63) == 0 && hd != 0) atomic_add_t<ST>(&a.hub_hd[h], hd);
+        __syncthreads();  // hist is cleared for the next slice
     }
-    hd = (ST)wave_sum_u64((unsigned long long)(int64_t)hd);
-    if ((threadIdx.x & 63) == 0 && hd != 0) atomic_add_t<ST>(&a.hub_hd[h], hd);
 }
 
 // Hubs, step 3: one workgroup per partition of a queued hub folds the
@@ -839,115 +847,120 @@ __global__ __launch_bounds__(256) void k_hub_part(MoveArgs<C> a)
     __shared__ uint64_t st_lo[40], st_hi[40];
     __shared__ int s_sp, s_cnt, s_over;
     if (*a.done) return;
-    const int gp = (int)blockIdx.x + a.part_base;
-    const int h = a.pown[gp];
-    if (!a.hub_act[h]) return;
-    const int v = a.binorder[a.list_begin + h];
-    const int dc = a.Cp[v];
-    const ST kv = a.K[v];
-    const int64_t Wv = vertex_W(a, v);
-    // candidates of this partition whose score bound cannot exceed staying are
-    // not read (the hub's weight to its own community is complete after k_hub_fill)
-    const SC floor = score_floor<C>(Wv, a.hub_hd[h], kv, a.Sig[dc]);
-    const int pb = a.poff[gp], pn = a.pcount[gp];
-    // table of 2^lg slots: twice the pairs (so no overflow) when that fits
-    int lg = 8;
-    while (lg < LOG2S && (1 << lg) < 2 * pn) ++lg;
-    const int Su = 1 << lg, capu = 3 * (Su / 4);
-    for (int s = threadIdx.x; s < Su; s += 256) {
-        keys[s] = -1;
-        vals[s] = 0;
-    }
-    if (threadIdx.x == 0) {
-        st_lo[0] = 0;
-        st_hi[0] = 1ull << 32;
-        s_sp = 1;
-    }
-    SC best = score_min<SC>();
-    int bc = INT_MAX;
-    ST hd = 0;
-    int nk = 0;
-    for (;;) {
-        __syncthreads();
-        const int sp = s_sp;
-        if (sp == 0) break;
-        const uint64_t lo = st_lo[sp - 1], hi = st_hi[sp - 1];
-        __syncthreads();
+    const int na = (int)*a.n_act_p;
+    for (int qi = blockIdx.x; qi < na; qi += gridDim.x) {  // uniform over the workgroup
+        const int gp = a.act_p[qi];
+        const int h = a.pown[gp];
+        if (!a.hub_act[h]) continue;
+        const int v = a.binorder[a.list_begin + h];
+        const int dc = a.Cp[v];
+        const ST kv = a.K[v];
+        const int64_t Wv = vertex_W(a, v);
+        // candidates of this partition whose score bound cannot exceed staying are
+        // not read (the hub's weight to its own community is complete after k_hub_fill)
+        const SC floor = score_floor<C>(Wv, a.hub_hd[h], kv, a.Sig[dc]);
+        const int pb = a.poff[gp], pn = a.pcount[gp];
+        // table of 2^lg slots: twice the pairs (so no overflow) when that fits
+        int lg = 8;
+        while (lg < LOG2S && (1 << lg) < 2 * pn) ++lg;
+        const int Su = 1 << lg, capu = 3 * (Su / 4);
+        for (int s = threadIdx.x; s < Su; s += 256) {
+            keys[s] = -1;
+            vals[s] = 0;
+        }
         if (threadIdx.x == 0) {
-            s_sp = sp - 1;
-            s_cnt = 0;
-            s_over = 0;
+            st_lo[0] = 0;
+            st_hi[0] = 1ull << 32;
+            s_sp = 1;
         }
-        __syncthreads();
-        const bool all = lo == 0 && hi == (1ull << 32);
-        for (int i0 = threadIdx.x; i0 < pn; i0 += 4 * 256) {
-            // four pairs per thread loaded together, then inserted
-            int32_t kq[4];
-            ST wq[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) kq[q] = i0 + q * 256 < pn ? a.pk[pb + i0 + q * 256] : -1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) wq[q] = kq[q] >= 0 ? a.pw[pb + i0 + q * 256] : (ST)0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t c = kq[q];
-                if (c < 0) continue;
-                if (!all) {
-                    const uint64_t x = hash32(mix32((uint32_t)c) ^ 0x5bd1e995u);
-                    if (x < lo || x >= hi) continue;
-                }
-                if (!lds_insert_capped<VT>(keys, vals, lg, c, (VT)wq[q], &s_cnt, capu)) s_over = 1;
-            }
-        }
-        __syncthreads();
-        if (s_over) {
-            // clear and split the range (a range of one hash value holds one key, so
-            // the splitting ends)
-            for (int s = threadIdx.x; s < Su; s += 256) {
-                keys[s] = -1;
-                vals[s] = 0;
-            }
+        SC best = score_min<SC>();
+        int bc = INT_MAX;
+        ST hd = 0;
+        int nk = 0;
+        for (;;) {
+            __syncthreads();
+            const int sp = s_sp;
+            if (sp == 0) break;
+            const uint64_t lo = st_lo[sp - 1], hi = st_hi[sp - 1];
+            __syncthreads();
             if (threadIdx.x == 0) {
-                const uint64_t mid = lo + (hi - lo) / 2;
-                st_lo[s_sp] = lo;
-                st_hi[s_sp] = mid;
-                st_lo[s_sp + 1] = mid;
-                st_hi[s_sp + 1] = hi;
-                s_sp += 2;
+                s_sp = sp - 1;
+                s_cnt = 0;
+                s_over = 0;
             }
-            continue;
-        }
-        for (int s0 = threadIdx.x; s0 < Su; s0 += 4 * 256) {
-            int kk[4];
-            ST xx[4], sg[4];
-            bool rd[4];
+            __syncthreads();
+            const bool all = lo == 0 && hi == (1ull << 32);
+            for (int i0 = threadIdx.x; i0 < pn; i0 += 4 * 256) {
+                // four pairs per thread loaded together, then inserted
+                int32_t kq[4];
+                ST wq[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int s = s0 + q * 256;
-                kk[q] = s < Su ? keys[s] : -1;
-                xx[q] = kk[q] >= 0 ? (ST)vals[s] : (ST)0;
-                if (kk[q] >= 0) {
+                for (int q = 0; q < 4; ++q) kq[q] = i0 + q * 256 < pn ? a.pk[pb + i0 + q * 256] : -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) wq[q] = kq[q] >= 0 ? a.pw[pb + i0 + q * 256] : (ST)0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t c = kq[q];
+                    if (c < 0) continue;
+                    if (!all) {
+                        const uint64_t x = hash32(mix32((uint32_t)c) ^ 0x5bd1e995u);
+                        if (x < lo || x >= hi) continue;
+                    }
+                    if (!lds_insert_capped<VT>(keys, vals, lg, c, (VT)wq[q], &s_cnt, capu)) s_over = 1;
+                }
+            }
+            __syncthreads();
+            if (s_over) {
+                // clear and split the range (a range of one hash value holds one key, so
+                // the splitting ends)
+                for (int s = threadIdx.x; s < Su; s += 256) {
                     keys[s] = -1;
                     vals[s] = 0;
                 }
-                rd[q] = kk[q] >= 0 && kk[q] != dc && worth_reading<C>(Wv, xx[q], floor);
-                nk += rd[q] ? 1 : 0;
+                if (threadIdx.x == 0) {
+                    const uint64_t mid = lo + (hi - lo) / 2;
+                    st_lo[s_sp] = lo;
+                    st_hi[s_sp] = mid;
+                    st_lo[s_sp + 1] = mid;
+                    st_hi[s_sp + 1] = hi;
+                    s_sp += 2;
+                }
+                continue;
             }
+            for (int s0 = threadIdx.x; s0 < Su; s0 += 4 * 256) {
+                int kk[4];
+                ST xx[4], sg[4];
+                bool rd[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sg[q] = rd[q] ? a.Sig[kk[q]] : (ST)0;
+                for (int q = 0; q < 4; ++q) {
+                    const int s = s0 + q * 256;
+                    kk[q] = s < Su ? keys[s] : -1;
+                    xx[q] = kk[q] >= 0 ? (ST)vals[s] : (ST)0;
+                    if (kk[q] >= 0) {
+                        keys[s] = -1;
+                        vals[s] = 0;
+                    }
+                    rd[q] = kk[q] >= 0 && kk[q] != dc && worth_reading<C>(Wv, xx[q], floor);
+                    nk += rd[q] ? 1 : 0;
+                }
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (rd[q] || kk[q] == dc) consider<C>(a, Wv, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+                for (int q = 0; q < 4; ++q) sg[q] = rd[q] ? a.Sig[kk[q]] : (ST)0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (rd[q] || kk[q] == dc)
+                        consider<C>(a, Wv, dc, kv, kk[q], xx[q], sg[q], best, bc, hd);
+            }
         }
-    }
-    block_reduce<SC, ST, 4>(r, best, bc, hd, nk);
-    if (threadIdx.x == 0) {
-        HubPart<C> p;
-        p.best = r.best[0];
-        p.bc = r.bc[0];
-        p.hd = r.hd[0];
-        p.nk = r.nonself[0];
-        ((HubPart<C> *)a.hpart)[gp] = p;
+        block_reduce<SC, ST, 4>(r, best, bc, hd, nk);
+        if (threadIdx.x == 0) {
+            HubPart<C> p;
+            p.best = r.best[0];
+            p.bc = r.bc[0];
+            p.hd = r.hd[0];
+            p.nk = r.nonself[0];
+            ((HubPart<C> *)a.hpart)[gp] = p;
+        }
+        __syncthreads();  // the table, the stack and r are reused by the next partition
     }
 }
 
@@ -1016,10 +1029,13 @@ template <class C>
 __global__ __launch_bounds__(256) void k_hub_mark(MoveArgs<C> a)
 {
     if (*a.done) return;
-    int h, v, beg, e0, e1, parts, gp0;
-    if (!hub_slice(a, (int)blockIdx.x + a.slice_base, &h, &v, &beg, &e0, &e1, &parts, &gp0)) return;
-    if (a.hub_act[h] != 2) return;
-    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) a.flags_next[a.tgt[beg + e]] = 1;
+    const int na = (int)*a.n_act_s;
+    for (int q = blockIdx.x; q < na; q += gridDim.x) {
+        int h, v, beg, e0, e1, parts, gp0;
+        if (!hub_slice(a, a.act_s[q], &h, &v, &beg, &e0, &e1, &parts, &gp0)) continue;
+        if (a.hub_act[h] != 2) continue;
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) a.flags_next[a.tgt[beg + e]] = 1;
+    }
 }
 
 template <class C, int BT, bool FAST>
@@ -1094,9 +1110,17 @@ void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int3
         launch_fill_i32(a.pcount + pb, 0, parts, s);
         launch_fill_i32(a.pcur + pb, 0, parts, s);
     }
-    k_hub_count<C><<<sort_slices, 256, 0, s>>>(a);
+    // the slices and partitions of the round's queued hubs: the sorting kernels loop
+    // over these lists instead of launching a workgroup for every slice of every hub
+    int32_t *tmp = a.act_tmp;
+    launch_hub_active_lists(a.hub_act, a.hslice, a.htslice, a.nhubs, a.hslices, a.htslices, tmp,
+                            tmp + a.nhubs, tmp + 2 * a.nhubs, tmp + 3 * a.nhubs, a.n_act_s,
+                            a.n_act_p, a.act_s, a.act_p, scratch, s);
+    const int gs = sort_slices < 8192 ? sort_slices : 8192;
+    const int gpt = parts < 4096 ? parts : 4096;
+    k_hub_count<C><<<gs, 256, 0, s>>>(a);
     launch_exclusive_scan<int32_t, int32_t>(a.pcount + pb, a.poff + pb, parts, scratch, nullptr, s);
-    k_hub_fill<C><<<sort_slices, 256, 0, s>>>(a);
+    k_hub_fill<C><<<gs, 256, 0, s>>>(a);
     const size_t bytes = ((size_t)1 << hub_plog2<ST>()) * (sizeof(typename C::VT) + 4);
     if (bytes > 65536) {
         // raise the dynamic-LDS limit of this kernel to what the launch asks for; a
@@ -1105,12 +1129,12 @@ void launch_move_hubs(bool fast, const MoveArgs<C> &a, int32_t sort_slices, int3
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
             (void)hipGetLastError();
     }
-    k_hub_part<C><<<parts, 256, bytes, s>>>(a);
+    k_hub_part<C><<<gpt, 256, bytes, s>>>(a);
     if (fast)
         k_move_hub<C, true><<<grid, HUB_THREADS, 0, s>>>(a);
     else
         k_move_hub<C, false><<<grid, HUB_THREADS, 0, s>>>(a);
-    k_hub_mark<C><<<sort_slices, 256, 0, s>>>(a);
+    k_hub_mark<C><<<gs, 256, 0, s>>>(a);
     launch_fill_u8(a.hub_act, 0, a.nhubs, s);  // every hub inactive again for the next round
 }
 template void launch_move_hubs<CfgNarrow>(bool, const MoveArgs<CfgNarrow> &, int32_t, int32_t,

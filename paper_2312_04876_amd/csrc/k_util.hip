@@ -1007,6 +1007,52 @@ void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s)
     if (n > 0) k_zero_u64<<<grid_for(n, 256), 256, 0, s>>>((unsigned long long *)p, n);
 }
 
+__global__ void k_hub_active_counts(const uint8_t *act, const int32_t *start_s,
+                                    const int32_t *start_p, int32_t hubs,
+                                    const unsigned long long *total_s,
+                                    const unsigned long long *total_p, int32_t *cs, int32_t *cp)
+{
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < hubs;
+         h += (int64_t)gridDim.x * blockDim.x) {
+        const bool on = act[h] != 0;
+        const int32_t es = h + 1 < hubs ? start_s[h + 1] : (int32_t)*total_s;
+        const int32_t ep = h + 1 < hubs ? start_p[h + 1] : (int32_t)*total_p;
+        cs[h] = on ? es - start_s[h] : 0;
+        cp[h] = on ? ep - start_p[h] : 0;
+    }
+}
+
+// One thread per hub writes its ranges (at most HUB_MAXP partitions and a few
+// hundred slices per hub).
+__global__ void k_hub_active_fill(const uint8_t *act, const int32_t *start_s,
+                                  const int32_t *start_p, int32_t hubs, const int32_t *cs,
+                                  const int32_t *cp, const int32_t *os, const int32_t *op,
+                                  int32_t *ls, int32_t *lp)
+{
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < hubs;
+         h += (int64_t)gridDim.x * blockDim.x) {
+        if (!act[h]) continue;
+        for (int32_t i = 0; i < cs[h]; ++i) ls[os[h] + i] = start_s[h] + i;
+        for (int32_t i = 0; i < cp[h]; ++i) lp[op[h] + i] = start_p[h] + i;
+    }
+}
+
+void launch_hub_active_lists(const uint8_t *act, const int32_t *start_s, const int32_t *start_p,
+                             int32_t hubs, const unsigned long long *total_s,
+                             const unsigned long long *total_p, int32_t *cs, int32_t *cp,
+                             int32_t *os, int32_t *op, unsigned long long *ns,
+                             unsigned long long *np, int32_t *ls, int32_t *lp, int64_t *scratch,
+                             hipStream_t s)
+{
+    if (hubs <= 0) return;
+    k_hub_active_counts<<<grid_for(hubs, 256), 256, 0, s>>>(act, start_s, start_p, hubs, total_s,
+                                                            total_p, cs, cp);
+    launch_exclusive_scan<int32_t, int32_t>(cs, os, hubs, scratch, ns, s);
+    launch_exclusive_scan<int32_t, int32_t>(cp, op, hubs, scratch, np, s);
+    k_hub_active_fill<<<grid_for(hubs, 256), 256, 0, s>>>(act, start_s, start_p, hubs, cs, cp, os,
+                                                          op, ls, lp);
+}
+
 void launch_owner_map(const int32_t *start, int32_t n, int32_t total, int32_t *owner, hipStream_t s)
 {
     if (n > 0 && total > 0) k_owner_map<<<grid_for(total, 256), 256, 0, s>>>(start, n, total, owner);

@@ -60,6 +60,17 @@ void launch_hub_move_sizes(const int32_t *binorder, int32_t hb, int32_t he, cons
                            int32_t *parts, hipStream_t s, int slice = HUB_PSLICE,
                            int per_part = 0);
 
+// The sorting slices and partitions of the queued hubs (act != 0) of a round, in hub
+// order: counts per hub (cs, cp), their exclusive scans (os, op; totals in *ns, *np)
+// and the lists (ls, lp).  start_s / start_p: first slice / partition per hub, totals
+// *total_s / *total_p (device).
+void launch_hub_active_lists(const uint8_t *act, const int32_t *start_s, const int32_t *start_p,
+                             int32_t hubs, const unsigned long long *total_s,
+                             const unsigned long long *total_p, int32_t *cs, int32_t *cp,
+                             int32_t *os, int32_t *op, unsigned long long *ns,
+                             unsigned long long *np, int32_t *ls, int32_t *lp, int64_t *scratch,
+                             hipStream_t s);
+
 // owner[k] = h for every k in [start[h], start[h + 1]) (the last range ends at
 // total): the hub, or hub community, of each sorting slice or partition, so the
 // sorting kernels read it instead of searching start[].
@@ -199,6 +210,10 @@ struct MoveArgs {
     const int32_t *hslice;             // first sorting slice per hub (HUB_PSLICE entries)
     const int32_t *htslice;            // first partition per hub
     const int32_t *sown, *pown;        // hub of each sorting slice / of each partition
+    int32_t *act_s, *act_p;            // sorting slices / partitions of the round's queued hubs
+    unsigned long long *n_act_s, *n_act_p;  // their counts
+    int32_t *act_tmp;                  // 4 * (hubs) ints: per-hub counts and offsets of the lists
+    const unsigned long long *hslices; // total sorting slices of the level
     const unsigned long long *htslices;  // total partitions
     int32_t slice_base, part_base;     // first sorting slice and partition of this launch's hubs
     int32_t *pcount, *pcur, *poff;     // pairs per partition, fill cursors, offsets

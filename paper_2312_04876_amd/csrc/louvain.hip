@@ -34,7 +34,8 @@ struct Layout {
     size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hstage, hstage_w, wcnt, pk, pw, hsz, hoff, scratch;
-    size_t bincnt, binoff, slA, slB, mpre, hub_act, hub_hd, hpart, pcnt, poff, sown, pown, wm0;
+    size_t bincnt, binoff, slA, slB, mpre, hub_act, hub_hd, hpart, pcnt, poff, sown, pown, wm0, act_s,
+        act_p, act_tmp;
     size_t colour, front, corder, kcnt, koff, cbm;  // colour-ordered mode
     int64_t kmax;                              // (colour, bin) keys that fit kcnt / koff
     size_t gid[3], gvb[3], gW, gsum, gst, giter, gcomm, gsig, gs2;  // batches
@@ -137,6 +138,11 @@ Layout make_layout(int32_t n, int64_t nnz, int sb, int32_t G = 0)
     L.pown = take(4 * parts);
     L.sown = take(4 * (z / 1024 + 64));
     L.wm0 = take(4 * (z / 1024 + 64));
+    // the round's queued hubs: their slices and partitions, and per-hub counts and
+    // offsets (fewer than nnz/2048 hubs)
+    L.act_s = take(4 * (z / 1024 + 64));
+    L.act_p = take(4 * parts);
+    L.act_tmp = take(4 * 4 * (z / 2048 + 64));
     L.total = cur;
     return L;
 }
@@ -276,6 +282,7 @@ struct louvain_ctx {
     void *hpart;
     int32_t *pcnt, *poff;
     int32_t *sown, *pown, *wm0;  // owners of hub slices / partitions, first member per window
+    int32_t *act_s, *act_p, *act_tmp;  // the round's queued hubs: slices, partitions, scratch
     int64_t owner_cap, part_cap; // their capacities
     uint8_t *hub_act;
     unsigned char *hub_hd;  // per hub: weight into its own community (moving, 4 or 8 bytes)
@@ -721,6 +728,12 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
     a.htslice = ctx->slB;
     a.sown = ctx->sown;
     a.pown = ctx->pown;
+    a.act_s = ctx->act_s;
+    a.act_p = ctx->act_p;
+    a.act_tmp = ctx->act_tmp;
+    a.n_act_s = &ctx->sc->act_slices;
+    a.n_act_p = &ctx->sc->act_parts;
+    a.hslices = &ctx->sc->hub_slices;
     a.htslices = &ctx->sc->hub_tslices;
     a.hpart = ctx->hpart;
     a.hub_act = ctx->hub_act;
@@ -1478,6 +1491,9 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->sown = (int32_t *)(b + L.sown);
     ctx->pown = (int32_t *)(b + L.pown);
     ctx->wm0 = (int32_t *)(b + L.wm0);
+    ctx->act_s = (int32_t *)(b + L.act_s);
+    ctx->act_p = (int32_t *)(b + L.act_p);
+    ctx->act_tmp = (int32_t *)(b + L.act_tmp);
     ctx->owner_cap = (nnz > 0 ? nnz : 1) / 1024 + 64;  // as sized in make_layout
     ctx->part_cap = (nnz > 0 ? nnz : 1) / 512 + 64;
     ctx->mpre = (int32_t *)(b + L.mpre);
