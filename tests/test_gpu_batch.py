@@ -93,6 +93,23 @@ def test_batch_coloured_equals_each_graph_alone_and_the_oracle():
         assert np.array_equal(parts[g], mo) and qs[g] == qo, csr.name
 
 
+def test_default_rounds_resolve_per_mode():
+    # round_bits -1 (the default) is 2 rounds in deterministic mode: the same result as
+    # round_bits 1, bit for bit, for one graph and for a batch
+    import paper_2312_04876_amd as P
+    csr = graphgen.workload("rmat14-16")
+    off, tgt, w = to_device(csr)
+    m_def, q_def, _ = P.louvain(off, tgt, w, mode="deterministic")
+    m_one, q_one, _ = P.louvain(off, tgt, w, mode="deterministic", round_bits=1)
+    assert np.array_equal(m_def.cpu().numpy(), m_one.cpu().numpy()) and q_def == q_one
+    graphs = [graphgen.sbm(500, 5, 0.1, 0.005, seed=31), graphgen.rmat(10, 8, seed=32)]
+    p_def, qs_def, _ = run_batch(graphs, mode="deterministic")
+    p_one, qs_one, _ = run_batch(graphs, mode="deterministic", round_bits=1)
+    for a, b in zip(p_def, p_one):
+        assert np.array_equal(a, b)
+    assert list(qs_def) == list(qs_one)
+
+
 @pytest.mark.parametrize("with_heavy_rows", [True, False])
 def test_batch_with_wide_totals_equals_each_graph_alone(with_heavy_rows):
     # heavy graphs push the union's total weight past 2^31, so the whole batch runs with
