@@ -144,7 +144,6 @@ struct DevScalars {
     int32_t bin_count[8];   // active vertices per bin in the current round
     int32_t bin_start[8];   // bin boundaries of the binning step (NBINS + 1 used)
     int32_t bin_maxlen[8];  // longest row per bin (binning step)
-    int32_t mv_count;       // deferred moves of the current round (deterministic mode)
     int32_t running;        // batches: graphs still moving after this iteration (then reset)
     unsigned long long kmax;  // wide input level: largest K' (level setup)
     // --- fields above are cleared at the start of every local-moving phase ---

@@ -61,6 +61,27 @@ __device__ inline void graph_gain(const MoveArgs<C> &a, int v, typename C::SC ga
     if (a.bt.gid) atomic_add_i128(a.bt.gsum + 2 * a.bt.gid[v], (i128)gain);
 }
 
+// The same for a whole wavefront (every lane calls this; gain 0 where the lane
+// adds nothing).  A wavefront's vertices are consecutive worklist entries, so
+// they nearly always lie in one or two graphs: the wavefront adds one sum per
+// graph it holds instead of one atomic per mover, which would all land on the
+// few graph sums that the vertices in flight share.
+template <class C>
+__device__ inline void wave_graph_gain(const MoveArgs<C> &a, int v, typename C::SC gain)
+{
+    if (!a.bt.gid) return;
+    const int g = gain != 0 ? a.bt.gid[v] : -1;
+    unsigned long long left = __ballot(g >= 0);
+    while (left) {
+        const int leader = __ffsll((long long)left) - 1;
+        const int gl = __shfl(g, leader, 64);
+        const bool mine = g == gl;
+        const i128 s = wave_sum_i128(mine ? (i128)gain : (i128)0);
+        if ((threadIdx.x & 63) == leader) atomic_add_i128(a.bt.gsum + 2 * gl, s);
+        left &= ~__ballot(mine);
+    }
+}
+
 // A community total or size as a decision reads it.  Fast mode reads the live
 // value coherently at agent scope (past the non-coherent L1 and the per-XCD
 // L2s): movers update totals with memory-side atomics and publish labels only
@@ -127,30 +148,18 @@ __device__ inline void fast_apply(const MoveArgs<C> &a, int v, int dc, int bc, t
 }
 
 // Commits the moves decided by the lanes with m set (one lane per vertex);
-// every lane of the wavefront calls this.  Deterministic mode appends them to
-// the round's move list (one list reservation per wavefront), applied when
-// the round ends.
+// every lane of the wavefront calls this.  Deterministic mode writes the new
+// label into the round's per-vertex move table (no vertex is decided twice in
+// a round), applied when the round ends.
 template <class C, bool FAST>
 __device__ inline void record_moves(const MoveArgs<C> &a, bool m, int v, int dc, int bc,
                                     typename C::ST kv)
 {
-    if (FAST) {
-        if (m) fast_apply<C>(a, v, dc, bc, kv);
-        return;
-    }
-    const unsigned long long b = __ballot(m);
-    if (b == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)b) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(a.mv_count, __popcll(b));
-    base = __shfl(base, leader, 64);
-    if (m) {
-        const int pos = base + __popcll(b & ((1ull << lane) - 1ull));
-        a.mv_v[pos] = v;
-        a.mv_c[pos] = bc;
-        a.mv_d[pos] = dc;
-    }
+    if (!m) return;
+    if (FAST)
+        fast_apply<C>(a, v, dc, bc, kv);
+    else
+        a.mv_c[v] = bc;
 }
 
 // The same for a single deciding thread.
@@ -158,14 +167,10 @@ template <class C, bool FAST>
 __device__ inline void record_move(const MoveArgs<C> &a, int v, int dc, int bc,
                                    typename C::ST kv)
 {
-    if (FAST) {
+    if (FAST)
         fast_apply<C>(a, v, dc, bc, kv);
-        return;
-    }
-    const int pos = atomicAdd(a.mv_count, 1);
-    a.mv_v[pos] = v;
-    a.mv_c[pos] = bc;
-    a.mv_d[pos] = dc;
+    else
+        a.mv_c[v] = bc;
 }
 
 // Fast mode, bins 0-3: a workgroup adds the community weight and size changes
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
         }
         SC gain = 0;
         const bool mv = has && decide<C, FAST>(a, Wv, dc, kv, best, bc, hd, nonself, sd, &gain);
-        if (mv && gl == 0) graph_gain<C>(a, v, gain);
+        wave_graph_gain<C>(a, v, mv && gl == 0 ? gain : (SC)0);
         if (has && gl == 0) {
             ++nv;
             if (mv) {

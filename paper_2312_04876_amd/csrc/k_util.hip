@@ -589,33 +589,33 @@ __device__ inline int apply_slot(int32_t *keys, int32_t c)
 }
 
 template <typename ST>
-__global__ __launch_bounds__(256) void k_apply(const int32_t *mv_v, const int32_t *mv_c,
-                                               const int32_t *mv_d, const int32_t *mv_count,
-                                               int32_t *Cp, const ST *K, ST *Sig, int32_t *size,
-                                               int32_t cap, const int32_t *done)
+__global__ __launch_bounds__(256) void k_apply(int32_t *mv_c, int32_t n, int32_t *Cp,
+                                               const ST *K, ST *Sig, int32_t *size,
+                                               const int32_t *done)
 {
     constexpr int S = 1 << APPLY_LOG2S;
     __shared__ int32_t keys[S];
     __shared__ ST dsig[S];
     __shared__ int32_t dsz[S];
     if (*done) return;
-    int m = *mv_count;
-    if (m > cap) m = cap;
-    if ((int64_t)blockIdx.x * APPLY_CHUNK >= m) return;
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
         keys[s] = -1;
         dsig[s] = 0;
         dsz[s] = 0;
     }
     __syncthreads();
-    for (int64_t base = (int64_t)blockIdx.x * APPLY_CHUNK; base < m;
+    for (int64_t base = (int64_t)blockIdx.x * APPLY_CHUNK; base < n;
          base += (int64_t)gridDim.x * APPLY_CHUNK) {
         for (int q = threadIdx.x; q < APPLY_CHUNK; q += blockDim.x) {
-            const int64_t k = base + q;
-            if (k >= m) break;
-            const int v = mv_v[k], c = mv_c[k], d = mv_d[k];
+            const int64_t v = base + q;
+            if (v >= n) break;
+            const int c = mv_c[v];
+            if (c < 0) continue;
+            // labels change only here, so Cp[v] is still the label the move was decided from
+            const int d = Cp[v];
             const ST kv = K[v];
             Cp[v] = c;
+            mv_c[v] = -1;
             const int sd = apply_slot(keys, d);
             atomic_add_t<ST>(&dsig[sd], (ST)-kv);
             atomicSub(&dsz[sd], 1);
@@ -645,7 +645,6 @@ __global__ void k_round_end(DevScalars *sc, int it)
         if (c) atomicAdd(&sc->processed[it], (unsigned long long)c);
         sc->bin_count[t] = 0;
     }
-    if (t == 0) sc->mv_count = 0;
 }
 
 __global__ __launch_bounds__(64) void k_iter_end(DevScalars *sc, int it, double tau, int batch)
@@ -1181,21 +1180,18 @@ void launch_compact_keys(const CompactArgs &a, const int32_t *koff, int32_t nkey
 }
 
 template <typename ST>
-void launch_apply(const int32_t *mv_v, const int32_t *mv_c, const int32_t *mv_d,
-                  const int32_t *mv_count, int32_t *Cp, const ST *K, ST *Sig, int32_t *size,
-                  int32_t cap, const int32_t *done, hipStream_t s)
+void launch_apply(int32_t *mv_c, int32_t n, int32_t *Cp, const ST *K, ST *Sig, int32_t *size,
+                  const int32_t *done, hipStream_t s)
 {
-    if (cap <= 0) return;
-    const int64_t chunks = ((int64_t)cap + APPLY_CHUNK - 1) / APPLY_CHUNK;
+    if (n <= 0) return;
+    const int64_t chunks = ((int64_t)n + APPLY_CHUNK - 1) / APPLY_CHUNK;
     const int grid = (int)std::min<int64_t>(chunks, 2048);
-    k_apply<ST><<<grid, 256, 0, s>>>(mv_v, mv_c, mv_d, mv_count, Cp, K, Sig, size, cap, done);
+    k_apply<ST><<<grid, 256, 0, s>>>(mv_c, n, Cp, K, Sig, size, done);
 }
-template void launch_apply<int32_t>(const int32_t *, const int32_t *, const int32_t *,
-                                    const int32_t *, int32_t *, const int32_t *, int32_t *,
-                                    int32_t *, int32_t, const int32_t *, hipStream_t);
-template void launch_apply<int64_t>(const int32_t *, const int32_t *, const int32_t *,
-                                    const int32_t *, int32_t *, const int64_t *, int64_t *,
-                                    int32_t *, int32_t, const int32_t *, hipStream_t);
+template void launch_apply<int32_t>(int32_t *, int32_t, int32_t *, const int32_t *, int32_t *,
+                                    int32_t *, const int32_t *, hipStream_t);
+template void launch_apply<int64_t>(int32_t *, int32_t, int32_t *, const int64_t *, int64_t *,
+                                    int32_t *, const int32_t *, hipStream_t);
 
 void launch_round_end(DevScalars *sc, int it, hipStream_t s)
 {

@@ -202,8 +202,7 @@ struct MoveArgs {
     typename C::ST *Sig;
     int32_t *size;
     uint8_t *flags_next;
-    int32_t *mv_v, *mv_c, *mv_d;       // deferred moves: vertex, new and old label
-    int32_t *mv_count;
+    int32_t *mv_c;                      // deferred moves: new label per vertex, -1 if none
     // hub bin: row entries are counting-sorted into partitions by community
     int32_t *hstage;                   // community of each hub entry (-1 between rounds)
     const int64_t *hoff;               // first staged entry per hub (scan of row lengths)
@@ -259,7 +258,6 @@ struct SeqArgs {
     int32_t *size;
     uint8_t *act;        // active flags of the level
     uint8_t *mark;       // deterministic mode: rows of this iteration's movers
-    int32_t *mv_v, *mv_c;  // deterministic mode: a round's moves (each graph in its range)
     int32_t n;           // vertices of the level (a single graph)
     int32_t max_n;       // largest graph moved here (at most SEQ_MAX)
     int64_t W;           // total weight (a single graph; a batch uses bt.gW)
@@ -275,16 +273,15 @@ struct SeqArgs {
 template <class C>
 void launch_seq_level(const SeqArgs<C> &a, bool fast, int graphs, hipStream_t s);
 
-// Deferred moves of a round (deterministic mode): each mover relabelled, and
-// the community weights and sizes updated, each workgroup combining the
-// updates of APPLY_CHUNK moves per community in LDS before one HBM atomic per
-// community.
+// Deferred moves of a round (deterministic mode): every vertex v < n with
+// mv_c[v] >= 0 relabelled to mv_c[v] (mv_c[v] reset to -1), the community
+// weights and sizes updated, each workgroup combining the updates of
+// APPLY_CHUNK vertices per community in LDS before one HBM atomic per community.
 template <typename ST>
-void launch_apply(const int32_t *mv_v, const int32_t *mv_c, const int32_t *mv_d,
-                  const int32_t *mv_count, int32_t *Cp, const ST *K, ST *Sig, int32_t *size,
-                  int32_t cap, const int32_t *done, hipStream_t s);
+void launch_apply(int32_t *mv_c, int32_t n, int32_t *Cp, const ST *K, ST *Sig, int32_t *size,
+                  const int32_t *done, hipStream_t s);
 
-// End of a round: processed += counts, counts = 0, mv_count = 0.
+// End of a round: processed += counts, counts = 0.
 void launch_round_end(DevScalars *sc, int it, hipStream_t s);
 // End of an iteration: folds the per-wavefront counter rows into the
 // iteration's gain sum, moves, scanned entries and the work counters, clears

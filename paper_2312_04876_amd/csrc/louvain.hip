@@ -30,7 +30,7 @@ struct Layout {
     size_t total;
     int sb;  // bytes of K', Sigma', table values and aggregated weights (4 or 8)
     int64_t scratch_elems;
-    size_t scalars, Cp, top, K, Sig, size, fa, fb, binorder, worklist, mv_v, mv_c, mv_d;
+    size_t scalars, Cp, top, K, Sig, size, fa, fb, binorder, worklist, vtmp, mv_c;
     size_t used, idmap, ccount, coff, ctot, cursor, members, cbinorder;
     size_t offA, offB, degA, degB, tgtA, tgtB, wA, wB;
     size_t hstage, hstage_w, wcnt, pk, pw, hsz, hoff, scratch;
@@ -68,9 +68,8 @@ Layout make_layout(int32_t n, int64_t nnz, int sb, int32_t G = 0)
     L.fb = take(n1);
     L.binorder = take(4 * n1);
     L.worklist = take(4 * n1);
-    L.mv_v = take(4 * n1);
+    L.vtmp = take(4 * n1);
     L.mv_c = take(4 * n1);
-    L.mv_d = take(4 * n1);
     L.used = take(4 * (n1 + 1));
     L.idmap = take(4 * (n1 + 1));
     L.ccount = take(4 * (n1 + 1));
@@ -269,7 +268,7 @@ struct louvain_ctx {
     bool noalloc;
     DevScalars own_hsc;
     int32_t own_done[LOUVAIN_MAX_ITERATIONS + 1];
-    int32_t *Cp, *top, *size, *binorder, *worklist, *mv_v, *mv_c, *mv_d;
+    int32_t *Cp, *top, *size, *binorder, *worklist, *vtmp, *mv_c;
     int32_t *used, *idmap, *ccount, *coff, *ctot, *cursor, *members, *cbinorder;
     uint8_t *fa, *fb;
     void *K, *Sig;
@@ -480,6 +479,7 @@ int setup_level(louvain_ctx *ctx)
         CKL();
     }
     launch_init_vertices(l.n, ctx->Cp, ctx->size, ctx->fa, ctx->fb, ctx->K, ctx->Sig, ctx->L.sb, s);
+    launch_fill_i32(ctx->mv_c, -1, l.n, s);  // no deferred move (deterministic rounds)
     launch_bin_count(l.n, l.off, l.deg, ctx->lds_max, ctx->bincnt, ctx->binoff, ctx->scratch,
                      ctx->sc->bin_start, ctx->sc->bin_maxlen, s);
     CKL();
@@ -641,10 +641,10 @@ int colour_level(louvain_ctx *ctx)
         // consecutive and a round launches the hub kernels over their slices only
         int32_t *hub_ids = ctx->binorder + ctx->bins.start[NBINS - 1];
         std::vector<int32_t> ids(hubs), col(hubs);
-        launch_gather_i32(ctx->colour, hub_ids, hubs, ctx->mv_v, s);  // mv_v is free until the rounds
+        launch_gather_i32(ctx->colour, hub_ids, hubs, ctx->vtmp, s);
         CKL();
         CK(hipMemcpyAsync(ids.data(), hub_ids, hubs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        CK(hipMemcpyAsync(col.data(), ctx->mv_v, hubs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(col.data(), ctx->vtmp, hubs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         std::vector<int32_t> idx(hubs);
         for (int h = 0; h < hubs; ++h) idx[h] = h;
@@ -712,11 +712,8 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
     a.K = (const ST *)ctx->K;
     a.Sig = (ST *)ctx->Sig;
     a.size = ctx->size;
-    a.mv_v = ctx->mv_v;
     a.mv_c = ctx->mv_c;
-    a.mv_d = ctx->mv_d;
     a.spread = &ctx->sc->spread[0][0];
-    a.mv_count = &ctx->sc->mv_count;
     a.hstage = ctx->hstage;
     a.pcount = ctx->pcnt;
     a.pcur = ctx->pcnt + ctx->hub_tslices;  // zeroed together with pcount every round
@@ -776,8 +773,6 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
         q.size = ctx->size;
         q.act = ctx->fa;  // the flags of iteration 0 (graphs left to the rounds keep theirs)
         q.mark = ctx->fb;
-        q.mv_v = ctx->mv_v;
-        q.mv_c = ctx->mv_c;
         q.rule = 1;
         q.seed = ctx->p.seed;
         q.round_bits = ctx->p.round_bits;
@@ -849,7 +844,6 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
         }
         for (int r = 0; r < rounds; ++r) {
             int rgrid[NBINS];
-            int32_t cap = ctx->nb;
             int32_t hub1 = 0;
             for (int b = 0; b < NBINS; ++b) rgrid[b] = grid[b];
             CompactArgs ca;
@@ -861,7 +855,6 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
                 ca.order = ctx->corder;
                 ca.q0 = ko[0];
                 ca.q1 = ko[NBINS];
-                cap = ca.q1 - ca.q0;
                 for (int b = 0; b < NBINS; ++b) {
                     const int per = move_rows_per_block(b);
                     const int64_t g = ((int64_t)ko[b + 1] - ko[b] + per - 1) / per;
@@ -926,9 +919,8 @@ int move_phase(louvain_ctx *ctx, bool level_ready = false)
             }
             TRY(prof_begin(ctx, &ev));
             if (!fast) {
-                launch_apply<ST>(ctx->mv_v, ctx->mv_c, ctx->mv_d, &ctx->sc->mv_count, ctx->Cp,
-                                 (const ST *)ctx->K, (ST *)ctx->Sig, ctx->size, cap,
-                                 &ctx->sc->done, s);
+                launch_apply<ST>(ctx->mv_c, l.n, ctx->Cp, (const ST *)ctx->K, (ST *)ctx->Sig,
+                                 ctx->size, &ctx->sc->done, s);
                 CKL();
             }
             launch_round_end(ctx->sc, it, s);
@@ -1454,9 +1446,8 @@ int init_ctx(louvain_ctx **out, int32_t G, const int32_t *graph_offsets, int32_t
     ctx->fb = b + L.fb;
     ctx->binorder = (int32_t *)(b + L.binorder);
     ctx->worklist = (int32_t *)(b + L.worklist);
-    ctx->mv_v = (int32_t *)(b + L.mv_v);
+    ctx->vtmp = (int32_t *)(b + L.vtmp);
     ctx->mv_c = (int32_t *)(b + L.mv_c);
-    ctx->mv_d = (int32_t *)(b + L.mv_d);
     ctx->used = (int32_t *)(b + L.used);
     ctx->idmap = (int32_t *)(b + L.idmap);
     ctx->ccount = (int32_t *)(b + L.ccount);
