@@ -97,8 +97,8 @@ constexpr int BIN_CHUNK = 4096;
 // Vertices per workgroup (and LDS table slots / 2) of the community counting kernels.
 constexpr int COMM_CHUNK = 2048;
 constexpr int COMM_LOG2S = 12;
-// Moves per workgroup step of the round-end apply kernel, and its LDS table
-// (2^APPLY_LOG2S slots >= twice the 2 * APPLY_CHUNK community keys).
+// Vertices per workgroup step of the round-end apply kernel, and its LDS table
+// (2^APPLY_LOG2S slots >= twice the 2 * APPLY_CHUNK community keys of their moves).
 constexpr int APPLY_CHUNK = 512;
 constexpr int APPLY_LOG2S = 11;
 // Local-moving counters are accumulated per wavefront into NSPREAD rows of

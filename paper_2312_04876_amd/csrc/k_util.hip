@@ -572,8 +572,9 @@ __global__ __launch_bounds__(256) void k_compact_keys(CompactArgs a, const int32
     if (lane == 0 && nact) atomicAdd(processed, nact);
 }
 
-// Slot of community c in the apply kernel's LDS table (inserted if absent).
-__device__ inline int apply_slot(int32_t *keys, int32_t c)
+// Slot of community c in the apply kernel's LDS table (inserted if absent; the
+// inserting thread appends the slot to the chunk's list of used slots).
+__device__ inline int apply_slot(int32_t *keys, int32_t c, int32_t *used, int32_t *nused)
 {
     constexpr uint32_t mask = (1u << APPLY_LOG2S) - 1u;
     uint32_t h = hash32((uint32_t)c) >> (32 - APPLY_LOG2S);
@@ -582,6 +583,7 @@ __device__ inline int apply_slot(int32_t *keys, int32_t c)
         if (k == c) return (int)h;
         if (k < 0) {
             const int32_t old = atomicCAS(&keys[h], -1, c);
+            if (old < 0) used[atomicAdd(nused, 1)] = (int32_t)h;
             if (old < 0 || old == c) return (int)h;
         }
         h = (h + 1) & mask;
@@ -597,12 +599,15 @@ __global__ __launch_bounds__(256) void k_apply(int32_t *mv_c, int32_t n, int32_t
     __shared__ int32_t keys[S];
     __shared__ ST dsig[S];
     __shared__ int32_t dsz[S];
+    __shared__ int32_t used[2 * APPLY_CHUNK];  // a chunk's movers name at most 2 * APPLY_CHUNK keys
+    __shared__ int32_t nused;
     if (*done) return;
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
         keys[s] = -1;
         dsig[s] = 0;
         dsz[s] = 0;
     }
+    if (threadIdx.x == 0) nused = 0;
     __syncthreads();
     for (int64_t base = (int64_t)blockIdx.x * APPLY_CHUNK; base < n;
          base += (int64_t)gridDim.x * APPLY_CHUNK) {
@@ -616,23 +621,27 @@ __global__ __launch_bounds__(256) void k_apply(int32_t *mv_c, int32_t n, int32_t
             const ST kv = K[v];
             Cp[v] = c;
             mv_c[v] = -1;
-            const int sd = apply_slot(keys, d);
+            const int sd = apply_slot(keys, d, used, &nused);
             atomic_add_t<ST>(&dsig[sd], (ST)-kv);
             atomicSub(&dsz[sd], 1);
-            const int sc = apply_slot(keys, c);
+            const int sc = apply_slot(keys, c, used, &nused);
             atomic_add_t<ST>(&dsig[sc], kv);
             atomicAdd(&dsz[sc], 1);
         }
         __syncthreads();
-        for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        // flush only the slots this chunk used
+        const int nu = nused;
+        for (int q = threadIdx.x; q < nu; q += blockDim.x) {
+            const int s = used[q];
             const int32_t key = keys[s];
-            if (key < 0) continue;
             if (dsig[s] != 0) atomic_add_t<ST>(&Sig[key], dsig[s]);
             if (dsz[s] != 0) atomicAdd(&size[key], dsz[s]);
             keys[s] = -1;
             dsig[s] = 0;
             dsz[s] = 0;
         }
+        __syncthreads();
+        if (threadIdx.x == 0) nused = 0;
         __syncthreads();
     }
 }
