@@ -39,7 +39,9 @@ namespace {
 // LDS of one wavefront: the graph's state (at most MAXV vertices), a table
 // of 2 * MAXV slots (a row has at most MAXV distinct communities) and the
 // list of the slots in use.  Two sizes: 256 vertices (small enough for many
-// wavefronts per CU) and SEQ_MAX.
+// wavefronts per CU) and SEQ_MAX.  The deterministic kernel keeps its round's
+// move list in LDS of its own, so the sequential one fits three graphs of
+// SEQ_MAX vertices per CU.
 template <class C, int MAXV>
 struct WaveLds {
     typedef typename C::ST ST;
@@ -57,8 +59,6 @@ struct WaveLds {
     int32_t len[MAXV];
     uint8_t act[MAXV];
     uint8_t mark[MAXV];
-    int32_t mv_v[MAXV];  // deterministic mode: a round's moves (vertex, community)
-    int32_t mv_c[MAXV];
     int32_t nlist, nmv;
 };
 
@@ -350,6 +350,7 @@ __global__ __launch_bounds__(64) void k_sync_level(SeqArgs<C> a)
 {
     typedef typename C::ST ST;
     __shared__ WaveLds<C, MAXV> t;
+    __shared__ int32_t mv_v[MAXV], mv_c[MAXV];  // a round's moves (vertex, community)
     const int lane = threadIdx.x;
     int vb, ve;
     int64_t W;
@@ -387,8 +388,8 @@ __global__ __launch_bounds__(64) void k_sync_level(SeqArgs<C> a)
                     if (wave_decide<C, MAXV>(a, t, vb, i, t.beg[i], d, cur, W, a.rule != 0, &bc,
                                        &gain)) {
                         if (lane == 0) {
-                            t.mv_v[t.nmv] = i;
-                            t.mv_c[t.nmv] = bc;
+                            mv_v[t.nmv] = i;
+                            mv_c[t.nmv] = bc;
                             t.nmv += 1;
                         }
                         sumN += gain;
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(64) void k_sync_level(SeqArgs<C> a)
             // the movers marked for the next iteration
             const int nm = t.nmv;
             for (int k = lane; k < nm; k += 64) {
-                const int i = t.mv_v[k], c = t.mv_c[k], dc = t.lab[i];
+                const int i = mv_v[k], c = mv_c[k], dc = t.lab[i];
                 const ST kv = t.k[i];
                 atomic_add_t<ST>(&t.sig[dc], (ST)-kv);
                 atomic_add_t<ST>(&t.sig[c], kv);
@@ -411,9 +412,9 @@ __global__ __launch_bounds__(64) void k_sync_level(SeqArgs<C> a)
                 atomicAdd(&t.size[c], 1);
             }
             wave_sync();
-            for (int k = lane; k < nm; k += 64) t.lab[t.mv_v[k]] = t.mv_c[k];
+            for (int k = lane; k < nm; k += 64) t.lab[mv_v[k]] = mv_c[k];
             for (int k = 0; k < nm; ++k) {
-                const int i = t.mv_v[k];
+                const int i = mv_v[k];
                 const int beg = t.beg[i], d = t.len[i];
                 for (int e = lane; e < d; e += 64) t.mark[a.tgt[beg + e] - vb] = 1;
             }
