@@ -376,6 +376,22 @@ __device__ inline void atomic_add_t<int64_t>(int64_t *p, int64_t v)
     atomicAdd((unsigned long long *)p, (unsigned long long)v);
 }
 
+// The same, returning the value before the add.
+template <typename T>
+__device__ inline T atomic_add_ret(T *p, T v);
+
+template <>
+__device__ inline int32_t atomic_add_ret<int32_t>(int32_t *p, int32_t v)
+{
+    return atomicAdd(p, v);
+}
+
+template <>
+__device__ inline int64_t atomic_add_ret<int64_t>(int64_t *p, int64_t v)
+{
+    return (int64_t)atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+
 template <typename SC>
 __device__ inline SC score_min();
 

@@ -147,6 +147,36 @@ __device__ inline void fast_apply(const MoveArgs<C> &a, int v, int dc, int bc, t
     live_store(&a.Cp[v], bc);
 }
 
+// Fast mode, bins 4-5 (one deciding thread per vertex): the join is checked
+// against the destination's total at the moment it is committed.  The atomic
+// add of K_v to Sigma'[bc] returns the total just before the join; if movers
+// that joined bc after the vertex read its total raised it, the score drops by
+// K_v times their weight, and a move that no longer beats staying is withdrawn
+// (the weight taken back out, no size or label written), as if the vertex had
+// been decided after them.  Otherwise the rest of the move follows, the label
+// last (fast_apply).  *gain is the gain over staying as decided; it becomes
+// the gain at the commit.
+template <class C>
+__device__ inline bool fast_commit(const MoveArgs<C> &a, int v, int dc, int bc, typename C::ST kv,
+                                   typename C::ST sg, typename C::SC *gain)
+{
+    typedef typename C::ST ST;
+    typedef typename C::SC SC;
+    const ST now = atomic_add_ret<ST>(&a.Sig[bc], kv);
+    const SC g = *gain - (SC)kv * ((SC)now - (SC)sg);
+    if (!(g > 0)) {
+        atomic_add_t<ST>(&a.Sig[bc], (ST)-kv);
+        return false;
+    }
+    *gain = g;
+    atomic_add_t<ST>(&a.Sig[dc], (ST)-kv);
+    atomicSub(&a.size[dc], 1);
+    atomicAdd(&a.size[bc], 1);
+    __builtin_amdgcn_s_waitcnt(0);  // the atomics have completed before the label is stored
+    live_store(&a.Cp[v], bc);
+    return true;
+}
+
 // Commits the moves decided by the lanes with m set (one lane per vertex);
 // every lane of the wavefront calls this.  Deterministic mode writes the new
 // label into the round's per-vertex move table (no vertex is decided twice in
@@ -539,24 +569,29 @@ __global__ __launch_bounds__(256) void k_move_wave(MoveArgs<C> a)
 }
 
 // Block-wide argmax over NW wavefronts; the result is left in r.*[0].
+// The best candidate's community total as scored travels with it (sg).
 template <typename SC, typename ST, int NW>
 struct BlockRed {
     SC best[NW];
     int bc[NW];
+    ST sg[NW];
     ST hd[NW];
     int nonself[NW];
     int move;
 };
 
 template <typename SC, typename ST, int NW>
-__device__ inline void block_reduce(BlockRed<SC, ST, NW> &r, SC best, int bc, ST hd, int nonself)
+__device__ inline void block_reduce(BlockRed<SC, ST, NW> &r, SC best, int bc, ST hd, int nonself,
+                                    ST sg = 0)
 {
     for (int o = 32; o > 0; o >>= 1) {
         const SC ob = shfl_xor_t<SC>(best, o);
         const int oc = __shfl_xor(bc, o, 64);
+        const ST og = shfl_xor_t<ST>(sg, o);
         if (better(ob, oc, best, bc)) {
             best = ob;
             bc = oc;
+            sg = og;
         }
         hd += shfl_xor_t<ST>(hd, o);
         nonself += __shfl_xor(nonself, o, 64);
@@ -565,6 +600,7 @@ __device__ inline void block_reduce(BlockRed<SC, ST, NW> &r, SC best, int bc, ST
     if ((threadIdx.x & 63) == 0) {
         r.best[wave] = best;
         r.bc[wave] = bc;
+        r.sg[wave] = sg;
         r.hd[wave] = hd;
         r.nonself[wave] = nonself;
     }
@@ -574,6 +610,7 @@ __device__ inline void block_reduce(BlockRed<SC, ST, NW> &r, SC best, int bc, ST
             if (better(r.best[k], r.bc[k], r.best[0], r.bc[0])) {
                 r.best[0] = r.best[k];
                 r.bc[0] = r.bc[k];
+                r.sg[0] = r.sg[k];
             }
             r.hd[0] += r.hd[k];
             r.nonself[0] += r.nonself[k];
@@ -657,6 +694,7 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
         SC floor = score_floor<C>(Wv, hd, kv, sd);
         SC best = score_min<SC>();
         int bc = INT_MAX;
+        ST sgb = 0;
         for (int ph = 0; ph < 2; ++ph) {
             for (int s0 = threadIdx.x; s0 < S; s0 += 4 * BT) {
                 int kk[4];
@@ -685,6 +723,7 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
                     if (better(sc, kk[q], best, bc)) {
                         best = sc;
                         bc = kk[q];
+                        sgb = sg[q];
                     }
                 }
             }
@@ -693,18 +732,19 @@ __global__ __launch_bounds__(BT) void k_move_block(MoveArgs<C> a, int log2s_max)
                 if (b1 > floor) floor = b1;
             }
         }
-        block_reduce<SC, ST, NW>(r, best, bc, threadIdx.x == 0 ? hd : (ST)0, nonself);
+        block_reduce<SC, ST, NW>(r, best, bc, threadIdx.x == 0 ? hd : (ST)0, nonself, sgb);
         if (threadIdx.x == 0) {
             SC gain = 0;
-            const bool mv = decide<C, FAST>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0],
-                                            sd, &gain);
+            bool mv = decide<C, FAST>(a, Wv, dc, kv, r.best[0], r.bc[0], r.hd[0], r.nonself[0], sd,
+                                      &gain);
+            if (FAST && mv) mv = fast_commit<C>(a, v, dc, r.bc[0], kv, r.sg[0], &gain);
             if (mv) graph_gain<C>(a, v, gain);
             r.move = mv ? 1 : 0;
             ++nv;
             if (mv) {
                 gain_acc += gain;
                 ++nm;
-                record_move<C, FAST>(a, v, dc, r.bc[0], kv);
+                if (!FAST) record_move<C, FAST>(a, v, dc, r.bc[0], kv);
             }
         }
         __syncthreads();
