@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--round-bits", type=int, default=None,
                     help="2^round_bits rounds per iteration (default: the library's, 3 in fast "
                          "mode on one graph, else 1)")
+    ap.add_argument("--small-level", type=int, default=0,
+                    help="batches: levels of a graph with at most this many vertices run in the "
+                         "small-level kernel (0: the library's default, -1: none)")
     ap.add_argument("--cpu-baseline", default="same",
                     help="workload the oracle is timed on: 'same' (the benchmark workload, "
                          "one whole run), a workload name, or 'none'")
@@ -344,11 +347,12 @@ def batch_main(args):
           file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     opts = dict(mode=args.mode, round_bits=args.round_bits)
+    sopts = dict(opts, small_level=args.small_level)  # the autotuner picks small_level itself
     off = torch.from_numpy(u.offsets32()).to(dev)
     tgt = torch.from_numpy(u.targets).to(dev)
     w = torch.from_numpy(u.weights).to(dev)
     memb = torch.empty(max(u.n, 1), dtype=torch.int32, device=dev)
-    uopts = dict(opts)
+    uopts = dict(sopts)
     tuned = None
     if args.autotune:
         from paper_2312_04876_amd import autotune
@@ -374,7 +378,7 @@ def batch_main(args):
         o = torch.from_numpy((u.offsets[a:b + 1] - e0).astype(np.int32)).to(dev)
         t = torch.from_numpy(u.targets[e0:e1] - np.int32(a)).to(dev)
         ww = torch.from_numpy(u.weights[e0:e1]).to(dev)
-        ctxs.append((P.Louvain(o, t, ww, **opts), torch.empty(max(b - a, 1), dtype=torch.int32,
+        ctxs.append((P.Louvain(o, t, ww, **sopts), torch.empty(max(b - a, 1), dtype=torch.int32,
                                                                device=dev)))
     q_s = [0.0] * args.batch
     torch.cuda.synchronize()
@@ -404,7 +408,8 @@ def batch_main(args):
                 "4..200 blocks, p_out/p_in 0.02, unit weights, seed 4" % (args.batch,
                                                                             args.batch_nmax),
         "config": {"workload": "batch%d" % args.batch, "graphs": args.batch, "n": u.n,
-                   "nnz": u.nnz, "mode": args.mode, "round_bits": args.round_bits},
+                   "nnz": u.nnz, "mode": args.mode, "round_bits": args.round_bits,
+                   "small_level": args.small_level},
         "one_by_one": {"value": u.nnz / sec_s, "ms": sec_s * 1e3},
         "autotune": tuned,
         "speedup": sec_s / sec_b,
