@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--round-bits", type=int, default=None,
                     help="2^round_bits rounds per iteration (default: the library's, 3 in fast "
                          "mode on one graph, else 1)")
+    ap.add_argument("--q-runs", type=int, default=0, metavar="K",
+                    help="after the timed runs, K more whole runs of the main workload whose "
+                         "modularities go into the line (fast mode is nondeterministic)")
     ap.add_argument("--small-level", type=int, default=0,
                     help="batches: levels of a graph with at most this many vertices run in the "
                          "small-level kernel (0: the library's default, -1: none)")
@@ -688,6 +691,11 @@ def measure(args, csr, name, steps, warmup):
     run_steps(ctx, memb, warmup)
     runs = []
     sec, (m, q, st) = run_steps(ctx, memb, steps, runs)
+    # untimed: more whole runs for the spread of a nondeterministic mode's modularity
+    q_more = []
+    for _ in range(args.q_runs if name == args.workload else 0):
+        ctx.reset()
+        q_more.append(ctx.run(memb)[1])
     # per pass (moving + renumbering + aggregation, Alg. 1), stepped through the C ABI
     # pass by pass with the host waiting after each: median over the timed runs
     per_pass = []
@@ -813,6 +821,11 @@ def measure(args, csr, name, steps, warmup):
         "modularity": q,
         "modularity_oracle_seq": q_ref,
         "modularity_delta_vs_oracle": (q - q_ref) if q_ref is not None else None,
+        "q_runs": ({"runs": len(q_more), "min": min(q_more), "median": float(np.median(q_more)),
+                    "max": max(q_more),
+                    "more_than_0.01_below_oracle_seq": (sum(1 for x in q_more if x < q_ref - 0.01)
+                                                        if q_ref is not None else None)}
+                   if q_more else None),
         "passes": st["passes"],
         "iterations": st["iterations"],
         "communities": st["communities"],
