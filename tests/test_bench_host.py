@@ -51,3 +51,21 @@ def test_copy_probe_calibration_is_recorded():
     data = json.load(open(os.path.join(ROOT, "profiles", "rmat24_fast_pmc.json")))
     # FETCH_SIZE counts half of what a plain copy reads on this part; WRITE_SIZE all it writes
     assert abs(data["fetch_factor"] - 2.0) < 0.05 and abs(data["write_factor"] - 1.0) < 0.05
+
+
+def test_pmc_summary_is_of_the_current_sources():
+    # the default line reads its traffic from this summary only while the sources it was
+    # measured on are the ones in the tree (else it reports traffic null)
+    data = json.load(open(os.path.join(ROOT, "profiles", "rmat24_fast_pmc.json")))
+    assert data["workload"] == "rmat24"
+    assert data["sources_sha256"] == bench.sources_digest()
+    fam = bench.measured_traffic("move_bin6_hub", os.path.join(ROOT, "profiles", "rmat24_fast_pmc.json"),
+                                 workload="rmat24")
+    assert fam is not None and fam > 0
+
+
+def test_default_arguments(monkeypatch):
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert (a.gpus, a.steps, a.warmup, a.workload, a.mode) == (1, 5, 2, "rmat24", "fast")
+    assert a.round_bits is None and a.q_runs == 0 and a.small_level == 0 and a.batch == 0
