@@ -443,8 +443,9 @@ def test_fast_quality(wl):
 
 def test_fast_quality_sbm():
     # SBM-10k is a deterministic-mode workload; in fast mode it must not fall more than
-    # 0.01 below the sequential oracle (it lands above it: the oracle's own Q varies by
-    # about 0.012 over vertex orders on this graph, see the golden relabelling runs)
+    # 0.01 below the sequential oracle (over 100 runs it lands 0.004-0.008 below it, inside
+    # the about 0.012 that the oracle's own Q varies over vertex orders on this graph, see
+    # the golden relabelling runs)
     assert _fast_q("sbm10k") >= _golden()["sbm10k"]["seq"]["Q"] - 0.01
 
 
