@@ -1,4 +1,6 @@
 """Host-side pieces of batches: the union of CSRs and the batched SBM recipe."""
+import os
+
 import numpy as np
 
 import graphgen
@@ -53,3 +55,35 @@ def test_perturb_deletes_and_inserts_a_share_of_edges():
     kept = sum(1 for a, b in old if a < b and (a, b) in pairs)
     assert abs((m - kept) - 0.1 * m) <= 0.02 * m + 2   # about a tenth deleted (re-inserts aside)
     assert graphgen.perturb(g, 0.0).targets.tolist() == g.targets.tolist()
+
+
+def test_batch_vs_oracle_script(tmp_path):
+    # the script behind the batch profile's oracle comparison: on a tiny batch whose "union"
+    # modularities are the oracle's own sequential results (and whose "one by one" ones are
+    # 0.02 lower for one graph) it counts what it should
+    import json
+    import subprocess
+    import sys
+
+    import oracle
+    here = os.path.dirname(os.path.abspath(__file__))
+    u, go, _ = graphgen.batch_sbm(6, seed=7, n_max=400)
+    qs = []
+    for g in range(6):
+        a, b = int(go[g]), int(go[g + 1])
+        e0, e1 = int(u.offsets[a]), int(u.offsets[b])
+        og = oracle.as_graph((u.offsets[a:b + 1] - e0).astype(np.int64),
+                             (u.targets[e0:e1] - np.int32(a)).astype(np.int32),
+                             u.weights[e0:e1].astype(np.int32))
+        qs.append(oracle.louvain(og, oracle.Params(mode="seq"))[1])
+    worse = list(qs)
+    worse[2] -= 0.02
+    path = tmp_path / "q.json"
+    path.write_text(json.dumps({"graphs": 6, "seed": 7, "batch_nmax": 400,
+                                "q_union": qs, "q_one_by_one": worse}))
+    out = subprocess.run([sys.executable, os.path.join(here, "golden", "batch_vs_oracle.py"),
+                          str(path), "--workers", "2"], capture_output=True, text=True,
+                         timeout=300, check=True).stdout
+    lines = [l for l in out.splitlines() if l.startswith("q_")]
+    assert "below -0.01: 0," in lines[0] and "equal: 6;" in lines[0]
+    assert "below -0.01: 1," in lines[1] and "equal: 5;" in lines[1]
